@@ -1,0 +1,207 @@
+/*
+ * scmc.h -- C ABI of libscmc: the two-component Shan-Chen lattice Boltzmann
+ * time step and its pressure-tensor observables on AMD Instinct MI355X
+ * (gfx950), after Lulli, Biferale, Falcucci, Sbragaglia, Shan, "Mesoscale
+ * Modelling of the Tolman Length in Multi-component Systems" (arXiv:2112.02574).
+ *
+ * The method (paper Sec. 2):
+ *   f_i^J(x + xi_i, t + 1) = f_i^J - (f_i^J - f_i^eq(n_J, u)) / tau_J
+ *                            + (1 - 1/(2 tau_J)) S_i(u, F_J)          (eq. lbm)
+ *   n_J = sum_i f_i^J;  (n_A + n_B) u = sum_J [sum_i f_i^J xi_i + F_J / 2]
+ *   F_J = -g_JK n_J sum_a W_a n_K(x + e_a) e_a
+ *         -g_JJ psi_J sum_a W_a psi_J(x + e_a) e_a                  (eq. sc_force)
+ * with a periodic box, D2Q9 or D3Q19 velocities (c_s^2 = 1/3) and force
+ * stencils of isotropy order 4 (the paper's W(1) = 1/6, W(2) = 1/12), 6 or 8,
+ * all normalised to e2 = sum_a W_a (e_a^x)^2 = 1 (Sec. 2, after eq. bulkp).
+ * The observables are the lattice pressure tensor (eq. sm:pt), the bulk
+ * pressure (eq. bulkp), the pressure jump dP, the generalised surface tension
+ * sigma[R] and the surface-of-tension radius R_s (Sec. 3, eq. gen_sigma), and
+ * the flat-interface sigma_0 (Sec. 4).
+ *
+ * Conventions
+ *   - Status: every call returns SCMC_OK (0) or a negative scmc_status.  No
+ *     C++ exception crosses this boundary.  scmc_last_error() gives the text
+ *     of the last failure on a handle.
+ *   - Memory: the library never allocates device memory.  The caller owns the
+ *     device workspace (size from scmc_workspace_bytes, any device pointer
+ *     with 256-byte alignment) and the HIP stream, both of which must outlive
+ *     the handle.  Host arrays passed in are borrowed for the duration of the
+ *     call only.  The library never frees caller memory.
+ *   - Layout of host fields: FP64, site index s = (z*ny + y)*nx + x (x
+ *     fastest), nz = 1 in 2D.  Population arrays are f[(J*Q + i)*N + s] with
+ *     J = 0 (A), 1 (B) and the velocity order given by scmc_velocities().
+ *   - State: the populations at integer time t are the pre-collision
+ *     (post-streaming) f_i^J(x, t) of eq. lbm; every getter and setter uses
+ *     that state.
+ *   - Streams: launches are asynchronous on the handle's stream; getters,
+ *     scmc_stats and scmc_observables synchronise that stream.
+ *   - Threads: one handle per host thread at a time; distinct handles are
+ *     independent.
+ */
+#ifndef SCMC_H
+#define SCMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCMC_OK = 0,
+    SCMC_EINVAL = -1,       /* NULL pointer, bad enum or size, tau <= 1/2,
+                               g_AB != g_BA, non-finite input */
+    SCMC_EUNSUPPORTED = -2, /* valid but not implemented (E8 in 3D,
+                               tau_A != tau_B, kernel design for this lattice) */
+    SCMC_ENOSPACE = -3,     /* workspace smaller than scmc_workspace_bytes */
+    SCMC_EDEVICE = -4,      /* HIP runtime error; see scmc_last_error */
+    SCMC_ENONFINITE = -5,   /* the state holds NaN or Inf */
+    SCMC_ESTATE = -6        /* call out of order (e.g. step before set) */
+} scmc_status;
+
+typedef enum { SCMC_D2Q9 = 0, SCMC_D3Q19 = 1 } scmc_lattice;
+typedef enum { SCMC_E4 = 4, SCMC_E6 = 6, SCMC_E8 = 8 } scmc_stencil;
+typedef enum { SCMC_PSI_N = 0, SCMC_PSI_EXP_NEG_INV = 1 } scmc_psi;
+typedef enum {
+    SCMC_F64 = 0,     /* populations stored and updated in FP64 */
+    SCMC_F32 = 1,     /* stored and updated in FP32 */
+    SCMC_F16_OFF = 2, /* stored as FP16 h = f - w_i n0_J (round to nearest
+                         even), updated in FP32 */
+    SCMC_BF16_OFF = 3 /* same with bfloat16 */
+} scmc_storage;
+typedef enum {
+    SCMC_KERNEL_AUTO = 0,     /* fused when available, else two-pass */
+    SCMC_KERNEL_TWO_PASS = 1, /* density pass + stream/force/collide pass */
+    SCMC_KERNEL_FUSED = 2     /* one z-marching kernel per step (D3Q19 with
+                                 E4/E6; D2Q9 with E4/E6/E8) */
+} scmc_kernel;
+typedef enum { SCMC_OBS_FLAT = 0, SCMC_OBS_DROPLET = 1 } scmc_obs_kind;
+
+typedef struct {
+    int lattice;      /* scmc_lattice */
+    int stencil;      /* scmc_stencil: isotropy order of the force stencil */
+    int nx, ny, nz;   /* periodic box; nz = 1 for D2Q9; every extent
+                         >= 2 r_F + 1 where r_F = 1 (E4) or 2 (E6, E8) */
+    double tau[2];    /* BGK relaxation times; must be equal (> 1/2) */
+    double g[2][2];   /* couplings G_JK c_s^2 multiplying the e2 = 1 stencil
+                         sums; g[0][1] == g[1][0] is the cross coupling */
+    int psi_self;     /* scmc_psi of the self terms; cross terms use n */
+    int storage;      /* scmc_storage */
+    double n0[2];     /* offset references of the FP16/BF16 storage */
+    int kernel;       /* scmc_kernel */
+    int tile[3];      /* fused-kernel tile (x, y, z-chunk); 0 = default */
+} scmc_problem;
+
+typedef struct {
+    double mass[2];      /* sum_x n_J */
+    double momentum[3];  /* sum_x sum_J (sum_i f_i xi_i + F_J / 2) */
+    double min_n[2];     /* min_x n_J */
+    double max_u;        /* max_x |u| */
+    double n_nonfinite;  /* number of non-finite populations */
+    int64_t step;        /* time t of the state */
+} scmc_stats;
+
+typedef struct {
+    double P_in, P_out;  /* bulk pressure (eq. bulkp) at the centre node
+                            floor(L/2) and at (centre + floor(L/2)) mod L */
+    double dP;           /* P_in - P_out */
+    double C_d;          /* int_0^{L/2} r^(d-1) (P_out - P_T(r)) dr along +x,
+                            P_T = P^yy, linear between nodes, exact per cell */
+    double R_s;          /* (d (d-1) C_d / dP)^(1/d): minimum of sigma[R] */
+    double sigma_s;      /* dP R_s / (d - 1): sigma at the minimum */
+    double R_s_grid;     /* parabolic-vertex minimum of sigma[R] on the grid
+                            [R0/2, 2 R0], step 0.01 (cross-check) */
+    double sigma0;       /* flat: sum_{x = nx/2}^{nx-1} (P^xx - P^yy), both
+                            averaged over y, z */
+    double max_PyyPzz;   /* max |P^yy - P^zz| on the droplet line (3D) */
+    int64_t step;
+} scmc_obs;
+
+/* Defaults: D3Q19, E6, 64^3, tau = 1, g_AB = 1.8, psi = n, FP32, auto. */
+int scmc_problem_init(scmc_problem *p);
+
+/* Velocity set of a lattice: xi[Q*3] (ints), w[Q]; returns Q or SCMC_EINVAL. */
+int scmc_velocities(int lattice, int *xi, double *w);
+
+/* Device workspace needed by a problem, in bytes (*out). */
+int scmc_workspace_bytes(const scmc_problem *p, size_t *out);
+
+typedef struct scmc_sim scmc_sim;
+
+/* Validate p and bind the caller's workspace (d_ws, ws_bytes) and HIP stream
+ * (a hipStream_t; NULL = the default stream).  Allocates no device memory.
+ * On failure *out is NULL. */
+int scmc_create(const scmc_problem *p, void *d_ws, size_t ws_bytes,
+                void *stream, scmc_sim **out);
+int scmc_destroy(scmc_sim *s);
+
+/* f_i^J(x, 0) = w_i n_J(x) (zero velocity; the paper does not state the
+ * initial populations), t = 0.  nA, nB: N host doubles each.  EINVAL on a
+ * non-finite value. */
+int scmc_set_density(scmc_sim *s, const double *nA, const double *nB);
+
+/* Advance nsteps >= 0 time steps, asynchronously.  With graph steps k > 0
+ * (scmc_set_graph_steps) runs of k steps replay one instantiated hipGraph. */
+int scmc_step(scmc_sim *s, int64_t nsteps);
+int scmc_set_graph_steps(scmc_sim *s, int k);
+int scmc_synchronize(scmc_sim *s);
+
+/* n_J(x, t) and, when u is not NULL, the common velocity u[c*N + s]
+ * (c = 0..2) of the current state.  Synchronous. */
+int scmc_get_fields(scmc_sim *s, double *nA, double *nB, double *u);
+
+/* Checkpoint / resume: f[2*Q*N] pre-collision populations and the step. */
+int scmc_get_populations(scmc_sim *s, double *f, int64_t *step);
+int scmc_set_populations(scmc_sim *s, const double *f, int64_t step);
+
+/* FP64 global statistics of the current state (Sec. 2 conservation laws). */
+int scmc_stats_get(scmc_sim *s, scmc_stats *out);
+
+/* Observables of the current state; PN, PT (nullable) receive P^xx, P^yy on
+ * the droplet line r = 0..floor(nx/2) (kind DROPLET, nx/2 + 1 values) or the
+ * transverse-averaged profiles (kind FLAT, nx values).  R0 sets the grid of
+ * the sigma[R] scan (DROPLET). */
+int scmc_observables(scmc_sim *s, int kind, double R0, scmc_obs *out,
+                     double *PN, double *PT);
+
+/* Many independent lattices advanced by one persistent launch per step
+ * (the paper's sweep over droplet sizes and couplings, Sec. 4).  Members may
+ * differ in size and couplings; they must share lattice, stencil, tau and
+ * storage.  Member calls take the member index i. */
+typedef struct scmc_batch scmc_batch;
+int scmc_batch_workspace_bytes(const scmc_problem *ps, int count, size_t *out);
+int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
+                      size_t ws_bytes, void *stream, scmc_batch **out);
+int scmc_batch_destroy(scmc_batch *b);
+int scmc_batch_set_density(scmc_batch *b, int i, const double *nA,
+                           const double *nB);
+int scmc_batch_step(scmc_batch *b, int64_t nsteps);
+int scmc_batch_set_graph_steps(scmc_batch *b, int k);
+int scmc_batch_get_fields(scmc_batch *b, int i, double *nA, double *nB,
+                          double *u);
+int scmc_batch_stats_get(scmc_batch *b, int i, scmc_stats *out);
+int scmc_batch_observables(scmc_batch *b, int i, int kind, double R0,
+                           scmc_obs *out, double *PN, double *PT);
+/* Tile (x, y, z-chunk) and persistent grid size in use. */
+int scmc_batch_config(scmc_batch *b, int *tile, int *grid);
+
+/* Autotuner: times each candidate fused-kernel tile on a scratch state in
+ * the handle's workspace (it overwrites the state, so call it before
+ * scmc_set_density), keeps the fastest, and returns it in tile[3].  When
+ * cache_path is not NULL the result is read from / appended to that text
+ * file, keyed by lattice, stencil, storage and box. */
+int scmc_autotune(scmc_sim *s, const char *cache_path, int *tile);
+int scmc_batch_autotune(scmc_batch *b, const char *cache_path, int *tile);
+
+/* Kernel design and tile in use by a handle. */
+int scmc_config(scmc_sim *s, int *kernel, int *tile);
+
+const char *scmc_last_error(const scmc_sim *s);
+const char *scmc_batch_last_error(const scmc_batch *b);
+const char *scmc_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,173 @@
+// lattice.h -- compile-time tables of the GPU library: velocity sets, lattice
+// weights and force stencils, plus the population storage formats.
+//
+// Velocity sets (paper Sec. 2): D3Q19 with c_s^2 = 1/3, and its 2D analogue
+// D2Q9.  Force stencils (eq. sc_force): vectors e_a with squared length s and
+// weight W(s), normalised so that e2 = sum_a W_a (e_a^x)^2 = 1 (Sec. 2, after
+// eq. bulkp).  Order 4 in 3D is the paper's W(1) = 1/6, W(2) = 1/12; the other
+// sets solve the isotropy conditions of the corresponding order:
+//   2D E4: W(1) = 1/3, W(2) = 1/12
+//   2D E6: W(1) = 4/15, W(2) = 1/10, W(4) = 1/120
+//   2D E8: W(1) = 4/21, W(2) = 4/45, W(4) = 1/60, W(5) = 2/315, W(8) = 1/5040
+//   3D E6: W(1) = 2/15, W(2) = 1/15, W(3) = 1/60, W(4) = 1/120
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace scmc {
+
+// ---------------------------------------------------------------- velocities
+template <int D> struct Lattice;
+
+template <> struct Lattice<2> {
+    static constexpr int D = 2;
+    static constexpr int Q = 9;
+    static constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static constexpr int CZ[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr double W[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,
+                                    1.0 / 9,  1.0 / 9,  1.0 / 36,
+                                    1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+
+template <> struct Lattice<3> {
+    static constexpr int D = 3;
+    static constexpr int Q = 19;
+    static constexpr int CX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1,
+                                   -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1,
+                                   1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0,
+                                   0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr double W[19] = {
+        1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+
+// ------------------------------------------------------------ force stencils
+constexpr double stencil_weight(int D, int order, int s) {
+    if (D == 2 && order == 4) return s == 1 ? 1.0 / 3 : s == 2 ? 1.0 / 12 : 0.0;
+    if (D == 2 && order == 6)
+        return s == 1 ? 4.0 / 15 : s == 2 ? 1.0 / 10 : s == 4 ? 1.0 / 120 : 0.0;
+    if (D == 2 && order == 8)
+        return s == 1   ? 4.0 / 21
+               : s == 2 ? 4.0 / 45
+               : s == 4 ? 1.0 / 60
+               : s == 5 ? 2.0 / 315
+               : s == 8 ? 1.0 / 5040
+                        : 0.0;
+    if (D == 3 && order == 4) return s == 1 ? 1.0 / 6 : s == 2 ? 1.0 / 12 : 0.0;
+    if (D == 3 && order == 6)
+        return s == 1   ? 2.0 / 15
+               : s == 2 ? 1.0 / 15
+               : s == 3 ? 1.0 / 60
+               : s == 4 ? 1.0 / 120
+                        : 0.0;
+    return 0.0;
+}
+
+constexpr int stencil_count(int D, int order) {
+    int n = 0;
+    for (int z = (D == 3 ? -2 : 0); z <= (D == 3 ? 2 : 0); ++z)
+        for (int y = -2; y <= 2; ++y)
+            for (int x = -2; x <= 2; ++x) {
+                int s = x * x + y * y + z * z;
+                if (s > 0 && stencil_weight(D, order, s) != 0.0) ++n;
+            }
+    return n;
+}
+
+template <int D, int ORDER> struct Stencil {
+    static constexpr int NE = stencil_count(D, ORDER);
+    static constexpr int R = ORDER == 4 ? 1 : 2;  // radius (max |e^k|)
+    struct Table {
+        int e[NE][3];
+        double W[NE];
+    };
+    static constexpr Table make() {
+        Table t{};
+        int n = 0;
+        for (int z = (D == 3 ? -2 : 0); z <= (D == 3 ? 2 : 0); ++z)
+            for (int y = -2; y <= 2; ++y)
+                for (int x = -2; x <= 2; ++x) {
+                    int s = x * x + y * y + z * z;
+                    double w = s > 0 ? stencil_weight(D, ORDER, s) : 0.0;
+                    if (w != 0.0) {
+                        t.e[n][0] = x;
+                        t.e[n][1] = y;
+                        t.e[n][2] = z;
+                        t.W[n] = w;
+                        ++n;
+                    }
+                }
+        return t;
+    }
+    static constexpr Table T = make();
+};
+
+// ----------------------------------------------------------- storage formats
+// load(p, i, ref) returns the population in compute precision; ref = w_i n0_J
+// is the offset reference (used by the FP16 / BF16 offset formats only).
+struct StoreF64 {
+    using T = double;
+    using R = double;
+    static constexpr int BYTES = 8;
+    __device__ __forceinline__ static R load(const T *p, long i, R) { return p[i]; }
+    __device__ __forceinline__ static void store(T *p, long i, R v, R) { p[i] = v; }
+    __host__ __device__ static double decode(T v, double) { return v; }
+};
+
+struct StoreF32 {
+    using T = float;
+    using R = float;
+    static constexpr int BYTES = 4;
+    __device__ __forceinline__ static R load(const T *p, long i, R) { return p[i]; }
+    __device__ __forceinline__ static void store(T *p, long i, R v, R) { p[i] = v; }
+    __host__ __device__ static double decode(T v, double) { return v; }
+};
+
+struct StoreF16 {
+    using T = uint16_t;
+    using R = float;
+    static constexpr int BYTES = 2;
+    __device__ __forceinline__ static R load(const T *p, long i, R ref) {
+        return __half2float(__ushort_as_half(p[i])) + ref;
+    }
+    __device__ __forceinline__ static void store(T *p, long i, R v, R ref) {
+        p[i] = __half_as_ushort(__float2half_rn(v - ref));
+    }
+};
+
+// bfloat16 = the top 16 bits of an IEEE binary32; rounding to nearest even
+__host__ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
+    uint32_t u;
+    __builtin_memcpy(&u, &v, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+__host__ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float v;
+    __builtin_memcpy(&v, &u, 4);
+    return v;
+}
+
+struct StoreBF16 {
+    using T = uint16_t;
+    using R = float;
+    static constexpr int BYTES = 2;
+    __device__ __forceinline__ static R load(const T *p, long i, R ref) {
+        return bf16_to_f32(p[i]) + ref;
+    }
+    __device__ __forceinline__ static void store(T *p, long i, R v, R ref) {
+        p[i] = f32_to_bf16_rne(v - ref);
+    }
+};
+
+}  // namespace scmc

@@ -1,0 +1,445 @@
+// obs_kernels.hip -- FP64 reductions on the current state: concentrations,
+// global statistics (mass, momentum, extrema, non-finite count), the common
+// velocity field, the lattice pressure tensor on the droplet axis and the
+// transverse-averaged flat profiles (paper Sec. 2 eq. sm:pt and eq. bulkp,
+// Sec. 3 eq. gen_sigma, Sec. 4).  Every reduction runs in a fixed order
+// (per-thread sequential, then a shared-memory tree, then one final block),
+// so repeated calls on the same state give bitwise-identical results.
+#include "site_ops.h"
+
+namespace scmc {
+
+constexpr int OB_BX = 64, OB_BY = 4, OB_THREADS = OB_BX * OB_BY;
+
+// Population value as a double: the stored value plus, for the offset
+// formats, the same single-precision reference the step kernels add.
+template <class ST> struct Decode;
+template <> struct Decode<StoreF64> {
+    __device__ static double get(const double *p, long i, double, double) {
+        return p[i];
+    }
+};
+template <> struct Decode<StoreF32> {
+    __device__ static double get(const float *p, long i, double, double) {
+        return (double)p[i];
+    }
+};
+template <> struct Decode<StoreF16> {
+    __device__ static double get(const uint16_t *p, long i, double w, double n0) {
+        const float ref = (float)w * (float)n0;
+        return (double)__half2float(__ushort_as_half(p[i])) + (double)ref;
+    }
+};
+template <> struct Decode<StoreBF16> {
+    __device__ static double get(const uint16_t *p, long i, double w, double n0) {
+        const float ref = (float)w * (float)n0;
+        return (double)bf16_to_f32(p[i]) + (double)ref;
+    }
+};
+
+template <int D, class ST>
+__device__ __forceinline__ void pull64(const Member &m,
+                                       const typename ST::T *__restrict__ src,
+                                       int x, int y, int z,
+                                       double (&f)[2][Lattice<D>::Q]) {
+    using L = Lattice<D>;
+    const typename ST::T *base = src + m.pop_off;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int xs = wrap1(x - L::CX[i], m.nx);
+        const int ys = wrap1(y - L::CY[i], m.ny);
+        const int zs = D == 3 ? wrap1(z - L::CZ[i], m.nz) : 0;
+        const long s = ((long)zs * m.ny + ys) * m.nx + xs;
+        f[0][i] = Decode<ST>::get(base, (long)i * m.N + s, L::W[i], m.n0[0]);
+        f[1][i] = Decode<ST>::get(base, (long)(L::Q + i) * m.N + s, L::W[i],
+                                  m.n0[1]);
+    }
+}
+
+template <int D, class ST>
+__global__ void __launch_bounds__(OB_THREADS)
+    k_density64(Member m, const typename ST::T *__restrict__ src,
+                double *__restrict__ dens) {
+    const int x = blockIdx.x * OB_BX + threadIdx.x;
+    const int y = blockIdx.y * OB_BY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= m.nx || y >= m.ny) return;
+    double f[2][Lattice<D>::Q];
+    pull64<D, ST>(m, src, x, y, z, f);
+    double nA, nB;
+    site_density<D, double>(f, nA, nB);
+    const long s = ((long)z * m.ny + y) * m.nx + x;
+    dens[s] = nA;
+    dens[m.N + s] = nB;
+}
+
+// stats slots: 0 mass A, 1 mass B, 2-4 momentum, 5 min n_A, 6 min n_B,
+// 7 max |u|, 8 non-finite count
+constexpr int NSTAT = 9;
+
+__device__ __forceinline__ double combine(int k, double a, double b) {
+    if (k == 5 || k == 6) return fmin(a, b);
+    if (k == 7) return fmax(a, b);
+    return a + b;
+}
+
+template <int D, int ORDER, class ST, int PSI>
+__global__ void __launch_bounds__(OB_THREADS)
+    k_stats(Member m, const typename ST::T *__restrict__ src,
+            const double *__restrict__ dens, double *__restrict__ partials) {
+    __shared__ double red[NSTAT][OB_THREADS];
+    const int tid = threadIdx.y * OB_BX + threadIdx.x;
+    const int x = blockIdx.x * OB_BX + threadIdx.x;
+    const int y = blockIdx.y * OB_BY + threadIdx.y;
+    const int z = blockIdx.z;
+    double v[NSTAT] = {0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
+    if (x < m.nx && y < m.ny) {
+        using L = Lattice<D>;
+        double f[2][L::Q];
+        pull64<D, ST>(m, src, x, y, z, f);
+        const long s = ((long)z * m.ny + y) * m.nx + x;
+        const double nA = dens[s], nB = dens[m.N + s];
+        double FA[3], FB[3];
+        site_force<D, ORDER, PSI, double>(m, dens, dens + m.N, x, y, z, nA,
+                                          nB, FA, FB);
+        double mom[3] = {0, 0, 0}, bad = 0;
+#pragma unroll
+        for (int J = 0; J < 2; ++J)
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                if (!isfinite(f[J][i])) bad += 1;
+                mom[0] += L::CX[i] * f[J][i];
+                mom[1] += L::CY[i] * f[J][i];
+                mom[2] += L::CZ[i] * f[J][i];
+            }
+        double uu = 0;
+        for (int c = 0; c < 3; ++c) {
+            mom[c] += 0.5 * (FA[c] + FB[c]);
+            const double u = mom[c] / (nA + nB);
+            uu += u * u;
+        }
+        v[0] = nA;
+        v[1] = nB;
+        v[2] = mom[0];
+        v[3] = mom[1];
+        v[4] = mom[2];
+        v[5] = nA;
+        v[6] = nB;
+        v[7] = sqrt(uu);
+        v[8] = bad;
+    }
+    for (int k = 0; k < NSTAT; ++k) red[k][tid] = v[k];
+    __syncthreads();
+    for (int h = OB_THREADS / 2; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int k = 0; k < NSTAT; ++k)
+                red[k][tid] = combine(k, red[k][tid], red[k][tid + h]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const long b = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x +
+                       blockIdx.x;
+        for (int k = 0; k < NSTAT; ++k) partials[b * NSTAT + k] = red[k][0];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+    k_stats_final(const double *__restrict__ partials, int nblocks,
+                  double *__restrict__ out) {
+    __shared__ double red[NSTAT][256];
+    const int tid = threadIdx.x;
+    double v[NSTAT] = {0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
+    for (int b = tid; b < nblocks; b += 256)
+        for (int k = 0; k < NSTAT; ++k)
+            v[k] = combine(k, v[k], partials[(long)b * NSTAT + k]);
+    for (int k = 0; k < NSTAT; ++k) red[k][tid] = v[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int k = 0; k < NSTAT; ++k)
+                red[k][tid] = combine(k, red[k][tid], red[k][tid + h]);
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int k = 0; k < NSTAT; ++k) out[k] = red[k][0];
+}
+
+template <int D, int ORDER, class ST, int PSI>
+__global__ void __launch_bounds__(OB_THREADS)
+    k_velocity64(Member m, const typename ST::T *__restrict__ src,
+                 const double *__restrict__ dens, double *__restrict__ u) {
+    const int x = blockIdx.x * OB_BX + threadIdx.x;
+    const int y = blockIdx.y * OB_BY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= m.nx || y >= m.ny) return;
+    using L = Lattice<D>;
+    double f[2][L::Q];
+    pull64<D, ST>(m, src, x, y, z, f);
+    const long s = ((long)z * m.ny + y) * m.nx + x;
+    const double nA = dens[s], nB = dens[m.N + s];
+    double FA[3], FB[3];
+    site_force<D, ORDER, PSI, double>(m, dens, dens + m.N, x, y, z, nA, nB,
+                                      FA, FB);
+    double mom[3] = {0, 0, 0};
+#pragma unroll
+    for (int J = 0; J < 2; ++J)
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            mom[0] += L::CX[i] * f[J][i];
+            mom[1] += L::CY[i] * f[J][i];
+            mom[2] += L::CZ[i] * f[J][i];
+        }
+    for (int c = 0; c < 3; ++c)
+        u[(long)c * m.N + s] = (mom[c] + 0.5 * (FA[c] + FB[c])) / (nA + nB);
+}
+
+// Lattice pressure tensor (eq. sm:pt) at one site, FP64:
+// P^mn = c_s^2 (n_A + n_B) delta^mn + 1/2 sum_a W_a e^m e^n
+//        [g_AB n_A n_B(x+e) + g_BA n_B n_A(x+e) + g_AA psi_A psi_A(x+e)
+//         + g_BB psi_B psi_B(x+e)]
+// returns xx, yy, zz
+template <int D, int ORDER, int PSI>
+__device__ void ptensor_diag(const Member &m, const double *__restrict__ dens,
+                             int x, int y, int z, double (&P)[3]) {
+    using S = Stencil<D, ORDER>;
+    const long s = ((long)z * m.ny + y) * m.nx + x;
+    const double nA = dens[s], nB = dens[m.N + s];
+    const double pA = psi_of<double, PSI>(nA), pB = psi_of<double, PSI>(nB);
+    double acc[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < S::NE; ++a) {
+        constexpr auto T = S::T;
+        const int e3[3] = {T.e[a][0], T.e[a][1], T.e[a][2]};
+        const int xs = wrap1(x + e3[0], m.nx);
+        const int ys = wrap1(y + e3[1], m.ny);
+        const int zs = D == 3 ? wrap1(z + e3[2], m.nz) : 0;
+        const long t = ((long)zs * m.ny + ys) * m.nx + xs;
+        const double nAt = dens[t], nBt = dens[m.N + t];
+        const double inter =
+            m.g[0][1] * nA * nBt + m.g[1][0] * nB * nAt +
+            m.g[0][0] * pA * psi_of<double, PSI>(nAt) +
+            m.g[1][1] * pB * psi_of<double, PSI>(nBt);
+        for (int k = 0; k < 3; ++k)
+            acc[k] += T.W[a] * (double)(e3[k] * e3[k]) * inter;
+    }
+    const double ideal = (nA + nB) / 3.0;
+    for (int k = 0; k < 3; ++k) P[k] = ideal + 0.5 * acc[k];
+}
+
+// Bulk pressure (eq. bulkp, e2 = 1) of the concentrations at one site.
+template <int PSI>
+__device__ double bulk_pressure(const Member &m, double nA, double nB) {
+    const double pA = psi_of<double, PSI>(nA), pB = psi_of<double, PSI>(nB);
+    return (nA + nB) / 3.0 + m.g[0][1] * nA * nB + 0.5 * m.g[0][0] * pA * pA +
+           0.5 * m.g[1][1] * pB * pB;
+}
+
+// One block: the axis line r = 0..rmax along +x from the centre node, the
+// two pressure probes, and C_d = int r^(d-1) (P_out - P_T) dr with P_T linear
+// between nodes (each cell integrated exactly).
+constexpr int LINE_THREADS = 256;
+template <int D, int ORDER, int PSI>
+__global__ void __launch_bounds__(LINE_THREADS)
+    k_line(Member m, const double *__restrict__ dens, double *__restrict__ out) {
+    __shared__ double red[LINE_THREADS];
+    const int cx = m.nx / 2, cy = m.ny / 2, cz = D == 3 ? m.nz / 2 : 0;
+    const int rmax = m.nx / 2;
+    const int tid = threadIdx.x;
+    const long sc = ((long)cz * m.ny + cy) * m.nx + cx;
+    const int ox = (cx + m.nx / 2) % m.nx, oy = (cy + m.ny / 2) % m.ny;
+    const int oz = D == 3 ? (cz + m.nz / 2) % m.nz : 0;
+    const long so = ((long)oz * m.ny + oy) * m.nx + ox;
+    const double Pout = bulk_pressure<PSI>(m, dens[so], dens[m.N + so]);
+    for (int r = tid; r <= rmax; r += LINE_THREADS) {
+        double P[3];
+        ptensor_diag<D, ORDER, PSI>(m, dens, (cx + r) % m.nx, cy, cz, P);
+        out[r] = P[0];
+        out[(rmax + 1) + r] = P[1];
+        out[2 * (rmax + 1) + r] = P[2];
+    }
+    __syncthreads();
+    // exact integral of r^(d-1) times the linear interpolant on [r, r+1]
+    double acc = 0;
+    const double mexp = D - 1;
+    for (int r = tid; r < rmax; r += LINE_THREADS) {
+        const double g0 = Pout - out[(rmax + 1) + r];
+        const double g1 = Pout - out[(rmax + 1) + r + 1];
+        const double a = r, b = r + 1.0;
+        const double I0 = (pow(b, mexp + 1) - pow(a, mexp + 1)) / (mexp + 1);
+        const double I1 =
+            (pow(b, mexp + 2) - pow(a, mexp + 2)) / (mexp + 2) - a * I0;
+        acc += g0 * I0 + (g1 - g0) * I1;
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int h = LINE_THREADS / 2; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out[3 * (rmax + 1)] = bulk_pressure<PSI>(m, dens[sc], dens[m.N + sc]);
+        out[3 * (rmax + 1) + 1] = Pout;
+        out[3 * (rmax + 1) + 2] = red[0];
+    }
+}
+
+// One block per x: transverse averages of P^xx and P^yy.
+constexpr int FLAT_THREADS = 256;
+template <int D, int ORDER, int PSI>
+__global__ void __launch_bounds__(FLAT_THREADS)
+    k_flat(Member m, const double *__restrict__ dens, double *__restrict__ out) {
+    __shared__ double rn[FLAT_THREADS], rt[FLAT_THREADS];
+    const int x = blockIdx.x, tid = threadIdx.x;
+    const int ntr = m.ny * m.nz;
+    double pn = 0, pt = 0;
+    for (int k = tid; k < ntr; k += FLAT_THREADS) {
+        double P[3];
+        ptensor_diag<D, ORDER, PSI>(m, dens, x, k % m.ny, k / m.ny, P);
+        pn += P[0];
+        pt += P[1];
+    }
+    rn[tid] = pn;
+    rt[tid] = pt;
+    __syncthreads();
+    for (int h = FLAT_THREADS / 2; h > 0; h >>= 1) {
+        if (tid < h) {
+            rn[tid] += rn[tid + h];
+            rt[tid] += rt[tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out[x] = rn[0] / ntr;
+        out[m.nx + x] = rt[0] / ntr;
+    }
+}
+
+// sigma0 = sum_{x = nx/2}^{nx-1} (P_N - P_T), sequential (nx <= a few 1000)
+__global__ void k_flat_sigma(int nx, double *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0;
+        for (int x = nx / 2; x < nx; ++x) s += out[x] - out[nx + x];
+        out[2 * nx] = s;
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+template <class F> static bool dispatch_all(const StepKey &k, F &&fn) {
+    auto with_st = [&](auto stv) {
+        auto go = [&](auto Dc, auto Oc) {
+            if (k.psi == 0)
+                fn(stv, Dc, Oc, std::integral_constant<int, 0>{});
+            else
+                fn(stv, Dc, Oc, std::integral_constant<int, 1>{});
+        };
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        using O4 = std::integral_constant<int, 4>;
+        using O6 = std::integral_constant<int, 6>;
+        using O8 = std::integral_constant<int, 8>;
+        if (k.dim == 2 && k.order == 4) return go(I2{}, O4{}), true;
+        if (k.dim == 2 && k.order == 6) return go(I2{}, O6{}), true;
+        if (k.dim == 2 && k.order == 8) return go(I2{}, O8{}), true;
+        if (k.dim == 3 && k.order == 4) return go(I3{}, O4{}), true;
+        if (k.dim == 3 && k.order == 6) return go(I3{}, O6{}), true;
+        return false;
+    };
+    switch (k.storage) {
+        case ST_F64: return with_st(StoreF64{});
+        case ST_F32: return with_st(StoreF32{});
+        case ST_F16: return with_st(StoreF16{});
+        case ST_BF16: return with_st(StoreBF16{});
+    }
+    return false;
+}
+
+static dim3 ob_grid(const Member &m) {
+    return dim3((m.nx + OB_BX - 1) / OB_BX, (m.ny + OB_BY - 1) / OB_BY, m.nz);
+}
+
+int stats_blocks(const Member &m) {
+    const dim3 g = ob_grid(m);
+    return (int)(g.x * g.y * g.z);
+}
+
+hipError_t launch_density64(const StepKey &k, const Member &m, const void *pop,
+                            double *dens64, hipStream_t st) {
+    hipError_t err = hipErrorInvalidValue;
+    dispatch_all(k, [&](auto stv, auto Dc, auto, auto) {
+        using ST = decltype(stv);
+        constexpr int D = decltype(Dc)::value;
+        hipLaunchKernelGGL((k_density64<D, ST>), ob_grid(m),
+                           dim3(OB_BX, OB_BY), 0, st, m,
+                           (const typename ST::T *)pop, dens64);
+        err = hipGetLastError();
+    });
+    return err;
+}
+
+hipError_t launch_stats(const StepKey &k, const Member &m, const void *pop,
+                        const double *dens64, double *partials, int nblocks_max,
+                        double *out, hipStream_t st) {
+    hipError_t err = hipErrorInvalidValue;
+    const int nb = stats_blocks(m);
+    if (nb > nblocks_max) return hipErrorInvalidValue;
+    dispatch_all(k, [&](auto stv, auto Dc, auto Oc, auto Pc) {
+        using ST = decltype(stv);
+        constexpr int D = decltype(Dc)::value;
+        constexpr int O = decltype(Oc)::value;
+        constexpr int P = decltype(Pc)::value;
+        hipLaunchKernelGGL((k_stats<D, O, ST, P>), ob_grid(m),
+                           dim3(OB_BX, OB_BY), 0, st, m,
+                           (const typename ST::T *)pop, dens64, partials);
+        hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, st, partials,
+                           nb, out);
+        err = hipGetLastError();
+    });
+    return err;
+}
+
+hipError_t launch_velocity64(const StepKey &k, const Member &m, const void *pop,
+                             const double *dens64, double *u, hipStream_t st) {
+    hipError_t err = hipErrorInvalidValue;
+    dispatch_all(k, [&](auto stv, auto Dc, auto Oc, auto Pc) {
+        using ST = decltype(stv);
+        constexpr int D = decltype(Dc)::value;
+        constexpr int O = decltype(Oc)::value;
+        constexpr int P = decltype(Pc)::value;
+        hipLaunchKernelGGL((k_velocity64<D, O, ST, P>), ob_grid(m),
+                           dim3(OB_BX, OB_BY), 0, st, m,
+                           (const typename ST::T *)pop, dens64, u);
+        err = hipGetLastError();
+    });
+    return err;
+}
+
+hipError_t launch_line(const StepKey &k, const Member &m, const double *dens64,
+                       double *out, hipStream_t st) {
+    hipError_t err = hipErrorInvalidValue;
+    dispatch_all(k, [&](auto, auto Dc, auto Oc, auto Pc) {
+        constexpr int D = decltype(Dc)::value;
+        constexpr int O = decltype(Oc)::value;
+        constexpr int P = decltype(Pc)::value;
+        hipLaunchKernelGGL((k_line<D, O, P>), dim3(1), dim3(LINE_THREADS), 0,
+                           st, m, dens64, out);
+        err = hipGetLastError();
+    });
+    return err;
+}
+
+hipError_t launch_flat(const StepKey &k, const Member &m, const double *dens64,
+                       double *out, hipStream_t st) {
+    hipError_t err = hipErrorInvalidValue;
+    dispatch_all(k, [&](auto, auto Dc, auto Oc, auto Pc) {
+        constexpr int D = decltype(Dc)::value;
+        constexpr int O = decltype(Oc)::value;
+        constexpr int P = decltype(Pc)::value;
+        hipLaunchKernelGGL((k_flat<D, O, P>), dim3(m.nx), dim3(FLAT_THREADS), 0,
+                           st, m, dens64, out);
+        hipLaunchKernelGGL(k_flat_sigma, dim3(1), dim3(64), 0, st, m.nx, out);
+        err = hipGetLastError();
+    });
+    return err;
+}
+
+}  // namespace scmc

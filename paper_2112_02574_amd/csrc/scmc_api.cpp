@@ -1,0 +1,1138 @@
+// scmc_api.cpp -- host side of libscmc: validation, workspace planning,
+// state transfer (with the pull-scheme index shift), launch sequencing,
+// explicit hipGraph construction, and the FP64 post-processing of the
+// pressure-tensor line (Sec. 3: closed-form minimum of sigma[R]).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/scmc.h"
+#include "lattice.h"
+#include "scmc_internal.h"
+
+using namespace scmc;
+
+// ------------------------------------------------------------------ helpers
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int lattice_q(int lattice) { return lattice == SCMC_D2Q9 ? 9 : 19; }
+int lattice_dim(int lattice) { return lattice == SCMC_D2Q9 ? 2 : 3; }
+int stencil_radius(int st) { return st == SCMC_E4 ? 1 : 2; }
+size_t storage_bytes(int st) {
+    return st == SCMC_F64 ? 8 : st == SCMC_F32 ? 4 : 2;
+}
+size_t real_bytes(int st) { return st == SCMC_F64 ? 8 : 4; }
+
+void velocities(int lattice, int *xi, double *w) {
+    if (lattice == SCMC_D2Q9) {
+        using L = Lattice<2>;
+        for (int i = 0; i < L::Q; ++i) {
+            xi[3 * i] = L::CX[i];
+            xi[3 * i + 1] = L::CY[i];
+            xi[3 * i + 2] = L::CZ[i];
+            w[i] = L::W[i];
+        }
+    } else {
+        using L = Lattice<3>;
+        for (int i = 0; i < L::Q; ++i) {
+            xi[3 * i] = L::CX[i];
+            xi[3 * i + 1] = L::CY[i];
+            xi[3 * i + 2] = L::CZ[i];
+            w[i] = L::W[i];
+        }
+    }
+}
+
+// IEEE binary16 round-to-nearest-even from binary32 (host).
+uint16_t f32_to_f16_rne(float v) {
+    uint32_t u;
+    std::memcpy(&u, &v, 4);
+    const uint32_t sign = (u >> 16) & 0x8000u;
+    const uint32_t exp = (u >> 23) & 0xffu;
+    uint32_t man = u & 0x7fffffu;
+    if (exp == 0xff) return (uint16_t)(sign | 0x7c00u | (man ? 0x200u : 0u));
+    int e = (int)exp - 127 + 15;
+    if (e >= 31) return (uint16_t)(sign | 0x7c00u);
+    if (e <= 0) {
+        if (e < -10) return (uint16_t)sign;
+        man |= 0x800000u;
+        const int shift = 14 - e;
+        uint32_t h = man >> shift;
+        const uint32_t rem = man & ((1u << shift) - 1);
+        const uint32_t half = 1u << (shift - 1);
+        if (rem > half || (rem == half && (h & 1u))) ++h;
+        return (uint16_t)(sign | h);
+    }
+    uint32_t h = ((uint32_t)e << 10) | (man >> 13);
+    const uint32_t rem = man & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) ++h;  // may carry
+    return (uint16_t)(sign | h);
+}
+
+float f16_to_f32(uint16_t h) {
+    const uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+    const uint32_t exp = (h >> 10) & 0x1fu;
+    uint32_t man = h & 0x3ffu;
+    uint32_t u;
+    if (exp == 0) {
+        if (man == 0) {
+            u = sign;
+        } else {
+            int e = -1;
+            do {
+                man <<= 1;
+                ++e;
+            } while (!(man & 0x400u));
+            u = sign | ((uint32_t)(127 - 15 - e) << 23) | ((man & 0x3ffu) << 13);
+        }
+    } else if (exp == 31) {
+        u = sign | 0x7f800000u | (man << 13);
+    } else {
+        u = sign | ((exp - 15 + 127) << 23) | (man << 13);
+    }
+    float v;
+    std::memcpy(&v, &u, 4);
+    return v;
+}
+
+// the single-precision offset reference used by the FP16 / BF16 formats
+float offset_ref(double w, double n0) { return (float)w * (float)n0; }
+
+void encode(int storage, double v, double w, double n0, void *dst, size_t i) {
+    switch (storage) {
+        case SCMC_F64: ((double *)dst)[i] = v; break;
+        case SCMC_F32: ((float *)dst)[i] = (float)v; break;
+        case SCMC_F16_OFF:
+            ((uint16_t *)dst)[i] =
+                f32_to_f16_rne((float)v - offset_ref(w, n0));
+            break;
+        default:
+            ((uint16_t *)dst)[i] =
+                f32_to_bf16_rne((float)v - offset_ref(w, n0));
+            break;
+    }
+}
+
+double decode(int storage, const void *src, size_t i, double w, double n0) {
+    switch (storage) {
+        case SCMC_F64: return ((const double *)src)[i];
+        case SCMC_F32: return ((const float *)src)[i];
+        case SCMC_F16_OFF:
+            return (double)f16_to_f32(((const uint16_t *)src)[i]) +
+                   (double)offset_ref(w, n0);
+        default:
+            return (double)bf16_to_f32(((const uint16_t *)src)[i]) +
+                   (double)offset_ref(w, n0);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ shared state
+struct Lat {
+    scmc_problem p;
+    Member m;
+    int q, dim;
+};
+
+struct Common {
+    StepKey key{};
+    int kernel = SCMC_KERNEL_TWO_PASS;
+    int tile[3] = {0, 0, 0};
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    void *pop[2] = {nullptr, nullptr};
+    void *dens = nullptr;
+    double *dens64 = nullptr;
+    double *vel64 = nullptr;
+    double *partials = nullptr;
+    double *small = nullptr;  // stats / line / flat outputs
+    int nblocks = 0;
+    int cur = 0;
+    int64_t step = 0;
+    bool initialized = false;
+    int graph_k = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+struct scmc_sim {
+    Common c;
+    Lat lat;
+};
+
+struct scmc_batch {
+    Common c;
+    std::vector<Lat> lats;
+    Member *d_members = nullptr;
+    Tile *d_tiles = nullptr;
+    int ntiles = 0;
+    int grid = 0;
+    std::vector<bool> member_set;
+};
+
+namespace {
+
+int fail(Common &c, int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c.err = buf;
+    return status;
+}
+
+#define HIPCHK(c, expr)                                                      \
+    do {                                                                     \
+        hipError_t e_ = (expr);                                              \
+        if (e_ != hipSuccess)                                                \
+            return fail((c), SCMC_EDEVICE, "%s: %s", #expr,                  \
+                        hipGetErrorString(e_));                              \
+    } while (0)
+
+int validate(const scmc_problem *p, std::string *why) {
+    char buf[256];
+    auto bad = [&](int st, const char *msg) {
+        if (why) *why = msg;
+        return st;
+    };
+    if (!p) return bad(SCMC_EINVAL, "problem is NULL");
+    if (p->lattice != SCMC_D2Q9 && p->lattice != SCMC_D3Q19)
+        return bad(SCMC_EINVAL, "unknown lattice");
+    if (p->stencil != SCMC_E4 && p->stencil != SCMC_E6 && p->stencil != SCMC_E8)
+        return bad(SCMC_EINVAL, "unknown stencil");
+    if (p->lattice == SCMC_D3Q19 && p->stencil == SCMC_E8)
+        return bad(SCMC_EUNSUPPORTED, "E8 stencil is 2D only");
+    if (p->storage < SCMC_F64 || p->storage > SCMC_BF16_OFF)
+        return bad(SCMC_EINVAL, "unknown storage");
+    if (p->psi_self != SCMC_PSI_N && p->psi_self != SCMC_PSI_EXP_NEG_INV)
+        return bad(SCMC_EINVAL, "unknown psi");
+    if (p->kernel < SCMC_KERNEL_AUTO || p->kernel > SCMC_KERNEL_FUSED)
+        return bad(SCMC_EINVAL, "unknown kernel design");
+    const int r = stencil_radius(p->stencil);
+    if (p->lattice == SCMC_D2Q9 && p->nz != 1)
+        return bad(SCMC_EINVAL, "nz must be 1 for D2Q9");
+    const int ext[3] = {p->nx, p->ny, p->nz};
+    for (int a = 0; a < (p->lattice == SCMC_D2Q9 ? 2 : 3); ++a)
+        if (ext[a] < 2 * r + 1) {
+            snprintf(buf, sizeof buf, "extent %d smaller than 2 r_F + 1 = %d",
+                     ext[a], 2 * r + 1);
+            if (why) *why = buf;
+            return SCMC_EINVAL;
+        }
+    if ((double)p->nx * p->ny * p->nz * 2 * lattice_q(p->lattice) > 2.0e9)
+        return bad(SCMC_EINVAL, "lattice too large for 32-bit plane indexing");
+    for (int J = 0; J < 2; ++J)
+        if (!std::isfinite(p->tau[J]) || !(p->tau[J] > 0.5))
+            return bad(SCMC_EINVAL, "tau must be finite and > 1/2");
+    if (p->tau[0] != p->tau[1])
+        return bad(SCMC_EUNSUPPORTED, "tau_A != tau_B is not supported");
+    for (int J = 0; J < 2; ++J)
+        for (int K = 0; K < 2; ++K)
+            if (!std::isfinite(p->g[J][K])) return bad(SCMC_EINVAL, "non-finite coupling");
+    if (p->g[0][1] != p->g[1][0]) return bad(SCMC_EINVAL, "g_AB != g_BA");
+    if (!std::isfinite(p->n0[0]) || !std::isfinite(p->n0[1]))
+        return bad(SCMC_EINVAL, "non-finite n0");
+    return SCMC_OK;
+}
+
+StepKey key_of(const scmc_problem &p) {
+    StepKey k;
+    k.dim = lattice_dim(p.lattice);
+    k.order = p.stencil;
+    k.storage = p.storage;
+    k.psi = p.psi_self;
+    return k;
+}
+
+Member member_of(const scmc_problem &p) {
+    Member m{};
+    m.nx = p.nx;
+    m.ny = p.ny;
+    m.nz = p.nz;
+    m.N = p.nx * p.ny * p.nz;
+    m.pop_off = 0;
+    m.dens_off = 0;
+    for (int J = 0; J < 2; ++J)
+        for (int K = 0; K < 2; ++K) m.g[J][K] = p.g[J][K];
+    m.omega = 1.0 / p.tau[0];
+    m.n0[0] = p.n0[0];
+    m.n0[1] = p.n0[1];
+    m.psi_self = p.psi_self;
+    m.self_on = (p.g[0][0] != 0.0 ? 1 : 0) | (p.g[1][1] != 0.0 ? 2 : 0);
+    return m;
+}
+
+// resolve the kernel design and the fused tile
+int choose_kernel(const scmc_problem &p, const StepKey &k, int *kernel,
+                  int *tile) {
+    int t[3] = {p.tile[0], p.tile[1], p.tile[2]};
+    if (p.kernel == SCMC_KERNEL_TWO_PASS) {
+        *kernel = SCMC_KERNEL_TWO_PASS;
+        tile[0] = tile[1] = tile[2] = 0;
+        return SCMC_OK;
+    }
+    if (t[0] == 0) {  // default fused tile
+        t[0] = 64;
+        t[1] = 4;
+        t[2] = 16;
+    }
+    if (fused_supported(k, t)) {
+        *kernel = SCMC_KERNEL_FUSED;
+        for (int a = 0; a < 3; ++a) tile[a] = t[a];
+        return SCMC_OK;
+    }
+    if (p.kernel == SCMC_KERNEL_FUSED) return SCMC_EUNSUPPORTED;
+    *kernel = SCMC_KERNEL_TWO_PASS;
+    tile[0] = tile[1] = tile[2] = 0;
+    return SCMC_OK;
+}
+
+struct Plan {
+    size_t pop, dens, dens64, vel64, partials, small, members, tiles, total;
+};
+
+Plan plan_of(const std::vector<scmc_problem> &ps, int ntiles) {
+    Plan pl{};
+    size_t pop = 0, dens = 0, nmax = 0, nxmax = 0;
+    int nb = 0;
+    for (const auto &p : ps) {
+        const size_t N = (size_t)p.nx * p.ny * p.nz;
+        pop += align_up(2 * (size_t)lattice_q(p.lattice) * N *
+                        storage_bytes(p.storage));
+        dens += align_up(2 * N * real_bytes(p.storage));
+        nmax = std::max(nmax, N);
+        nxmax = std::max(nxmax, (size_t)p.nx);
+        nb = std::max(nb, stats_blocks(member_of(p)));
+    }
+    pl.pop = pop;
+    pl.dens = dens;
+    pl.dens64 = align_up(2 * nmax * 8);
+    pl.vel64 = align_up(3 * nmax * 8);
+    pl.partials = align_up((size_t)nb * 9 * 8);
+    pl.small = align_up((3 * (nxmax / 2 + 1) + 3 + 2 * nxmax + 1 + 16) * 8);
+    pl.members = ps.size() > 1 ? align_up(ps.size() * sizeof(Member)) : 0;
+    pl.tiles = ntiles > 0 ? align_up((size_t)ntiles * sizeof(Tile)) : 0;
+    pl.total = 2 * pl.pop + pl.dens + pl.dens64 + pl.vel64 + pl.partials +
+               pl.small + pl.members + pl.tiles;
+    return pl;
+}
+
+void bind(Common &c, const Plan &pl, char *ws, int nblocks) {
+    char *p = ws;
+    c.pop[0] = p;
+    p += pl.pop;
+    c.pop[1] = p;
+    p += pl.pop;
+    c.dens = p;
+    p += pl.dens;
+    c.dens64 = (double *)p;
+    p += pl.dens64;
+    c.vel64 = (double *)p;
+    p += pl.vel64;
+    c.partials = (double *)p;
+    p += pl.partials;
+    c.small = (double *)p;
+    p += pl.small;
+    c.nblocks = nblocks;
+}
+
+void drop_graphs(Common &c) {
+    for (int k = 0; k < 2; ++k)
+        if (c.gexec[k]) {
+            (void)hipGraphExecDestroy(c.gexec[k]);
+            c.gexec[k] = nullptr;
+        }
+}
+
+// ---- state transfer (single lattice member) ----------------------------
+// the device buffer holds g_i(x) = f_i(x + xi_i): the post-collision values
+// that the next step pulls
+int upload_state(Common &c, const Lat &L, const double *f, void *dst_dev) {
+    const scmc_problem &p = L.p;
+    const int q = L.q;
+    const size_t N = (size_t)L.m.N;
+    int xi[57];
+    double w[19];
+    velocities(p.lattice, xi, w);
+    const size_t sb = storage_bytes(p.storage);
+    std::vector<unsigned char> host(2 * q * N * sb);
+    for (int J = 0; J < 2; ++J)
+        for (int i = 0; i < q; ++i) {
+            const double *src = f + ((size_t)J * q + i) * N;
+            const size_t base = ((size_t)J * q + i) * N;
+            for (int z = 0; z < p.nz; ++z)
+                for (int y = 0; y < p.ny; ++y) {
+                    const int zs = (z + xi[3 * i + 2] + p.nz) % p.nz;
+                    const int ys = (y + xi[3 * i + 1] + p.ny) % p.ny;
+                    for (int x = 0; x < p.nx; ++x) {
+                        const int xs = (x + xi[3 * i] + p.nx) % p.nx;
+                        const double v =
+                            src[((size_t)zs * p.ny + ys) * p.nx + xs];
+                        encode(p.storage, v, w[i], p.n0[J], host.data(),
+                               base + ((size_t)z * p.ny + y) * p.nx + x);
+                    }
+                }
+        }
+    HIPCHK(c, hipMemcpyAsync(dst_dev, host.data(), host.size(),
+                             hipMemcpyHostToDevice, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    return SCMC_OK;
+}
+
+int download_state(Common &c, const Lat &L, const void *src_dev, double *f) {
+    const scmc_problem &p = L.p;
+    const int q = L.q;
+    const size_t N = (size_t)L.m.N;
+    int xi[57];
+    double w[19];
+    velocities(p.lattice, xi, w);
+    const size_t sb = storage_bytes(p.storage);
+    std::vector<unsigned char> host(2 * q * N * sb);
+    HIPCHK(c, hipMemcpyAsync(host.data(), src_dev, host.size(),
+                             hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    for (int J = 0; J < 2; ++J)
+        for (int i = 0; i < q; ++i) {
+            double *dst = f + ((size_t)J * q + i) * N;
+            const size_t base = ((size_t)J * q + i) * N;
+            for (int z = 0; z < p.nz; ++z)
+                for (int y = 0; y < p.ny; ++y) {
+                    const int zs = (z - xi[3 * i + 2] + p.nz) % p.nz;
+                    const int ys = (y - xi[3 * i + 1] + p.ny) % p.ny;
+                    for (int x = 0; x < p.nx; ++x) {
+                        const int xs = (x - xi[3 * i] + p.nx) % p.nx;
+                        dst[((size_t)z * p.ny + y) * p.nx + x] = decode(
+                            p.storage, host.data(),
+                            base + ((size_t)zs * p.ny + ys) * p.nx + xs, w[i],
+                            p.n0[J]);
+                    }
+                }
+        }
+    return SCMC_OK;
+}
+
+int set_density_impl(Common &c, const Lat &L, const double *nA,
+                     const double *nB, void *dst_dev) {
+    const size_t N = (size_t)L.m.N;
+    const int q = L.q;
+    int xi[57];
+    double w[19];
+    velocities(L.p.lattice, xi, w);
+    for (size_t s = 0; s < N; ++s)
+        if (!std::isfinite(nA[s]) || !std::isfinite(nB[s]))
+            return fail(c, SCMC_EINVAL, "non-finite density at site %zu", s);
+    std::vector<double> f(2 * q * N);
+    for (int i = 0; i < q; ++i)
+        for (size_t s = 0; s < N; ++s) {
+            f[(size_t)i * N + s] = w[i] * nA[s];
+            f[((size_t)q + i) * N + s] = w[i] * nB[s];
+        }
+    return upload_state(c, L, f.data(), dst_dev);
+}
+
+// ---- observables of one member (its populations at pop_dev) ------------
+int member_obs_prep(Common &c, const Lat &L, const void *pop_dev) {
+    Member m = L.m;  // the dens64 scratch is per call, offset-free
+    m.dens_off = 0;
+    HIPCHK(c, launch_density64(c.key, m, pop_dev, c.dens64, c.stream));
+    return SCMC_OK;
+}
+
+Member obs_member(const Lat &L) {
+    Member m = L.m;
+    m.dens_off = 0;
+    return m;
+}
+
+int stats_impl(Common &c, const Lat &L, const void *pop_base, scmc_stats *out,
+               int64_t step) {
+    if (!out) return fail(c, SCMC_EINVAL, "out is NULL");
+    const Member m = obs_member(L);
+    int rc = member_obs_prep(c, L, pop_base);
+    if (rc) return rc;
+    HIPCHK(c, launch_stats(c.key, m, pop_base, c.dens64, c.partials,
+                           c.nblocks, c.small, c.stream));
+    double h[9];
+    HIPCHK(c, hipMemcpyAsync(h, c.small, sizeof h, hipMemcpyDeviceToHost,
+                             c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    out->mass[0] = h[0];
+    out->mass[1] = h[1];
+    out->momentum[0] = h[2];
+    out->momentum[1] = h[3];
+    out->momentum[2] = h[4];
+    out->min_n[0] = h[5];
+    out->min_n[1] = h[6];
+    out->max_u = h[7];
+    out->n_nonfinite = h[8];
+    out->step = step;
+    return SCMC_OK;
+}
+
+int fields_impl(Common &c, const Lat &L, const void *pop_base, double *nA,
+                double *nB, double *u) {
+    const Member m = obs_member(L);
+    const size_t N = (size_t)m.N;
+    int rc = member_obs_prep(c, L, pop_base);
+    if (rc) return rc;
+    if (nA)
+        HIPCHK(c, hipMemcpyAsync(nA, c.dens64, N * 8, hipMemcpyDeviceToHost,
+                                 c.stream));
+    if (nB)
+        HIPCHK(c, hipMemcpyAsync(nB, c.dens64 + N, N * 8,
+                                 hipMemcpyDeviceToHost, c.stream));
+    if (u) {
+        HIPCHK(c, launch_velocity64(c.key, m, pop_base, c.dens64, c.vel64,
+                                    c.stream));
+        HIPCHK(c, hipMemcpyAsync(u, c.vel64, 3 * N * 8, hipMemcpyDeviceToHost,
+                                 c.stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    return SCMC_OK;
+}
+
+int obs_impl(Common &c, const Lat &L, const void *pop_base, int kind, double R0,
+             scmc_obs *out, double *PN, double *PT, int64_t step) {
+    if (!out) return fail(c, SCMC_EINVAL, "out is NULL");
+    if (kind != SCMC_OBS_FLAT && kind != SCMC_OBS_DROPLET)
+        return fail(c, SCMC_EINVAL, "unknown observable kind %d", kind);
+    const Member m = obs_member(L);
+    const int d = L.dim;
+    std::memset(out, 0, sizeof *out);
+    out->step = step;
+    int rc = member_obs_prep(c, L, pop_base);
+    if (rc) return rc;
+    if (kind == SCMC_OBS_FLAT) {
+        const int nx = m.nx;
+        std::vector<double> h(2 * nx + 1);
+        HIPCHK(c, launch_flat(c.key, m, c.dens64, c.small, c.stream));
+        HIPCHK(c, hipMemcpyAsync(h.data(), c.small, h.size() * 8,
+                                 hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(c, hipStreamSynchronize(c.stream));
+        out->sigma0 = h[2 * nx];
+        if (PN) std::memcpy(PN, h.data(), nx * 8);
+        if (PT) std::memcpy(PT, h.data() + nx, nx * 8);
+        return SCMC_OK;
+    }
+    if (!(R0 > 0) || !std::isfinite(R0))
+        return fail(c, SCMC_EINVAL, "R0 must be positive");
+    const int rmax = m.nx / 2, nl = rmax + 1;
+    std::vector<double> h(3 * nl + 3);
+    HIPCHK(c, launch_line(c.key, m, c.dens64, c.small, c.stream));
+    HIPCHK(c, hipMemcpyAsync(h.data(), c.small, h.size() * 8,
+                             hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    const double Pin = h[3 * nl], Pout = h[3 * nl + 1], Cd = h[3 * nl + 2];
+    const double dP = Pin - Pout;
+    out->P_in = Pin;
+    out->P_out = Pout;
+    out->dP = dP;
+    out->C_d = Cd;
+    // sigma[R] = C_d / R^(d-1) + dP R / d  (Heaviside part of eq. gen_sigma
+    // integrated exactly); minimum at R_s = (d (d-1) C_d / dP)^(1/d)
+    out->R_s = std::pow(d * (d - 1) * Cd / dP, 1.0 / d);
+    out->sigma_s = dP * out->R_s / (d - 1);
+    const int nR = (int)std::floor((2.0 * R0 - 0.5 * R0) / 0.01) + 1;
+    std::vector<double> sg(nR);
+    int kb = 0;
+    for (int k = 0; k < nR; ++k) {
+        const double R = 0.5 * R0 + 0.01 * k;
+        sg[k] = Cd / std::pow(R, d - 1) + dP * R / d;
+        if (sg[k] < sg[kb]) kb = k;
+    }
+    double Rg = 0.5 * R0 + 0.01 * kb;
+    if (kb > 0 && kb < nR - 1) {
+        const double den = sg[kb - 1] - 2 * sg[kb] + sg[kb + 1];
+        if (den != 0) Rg += 0.01 * 0.5 * (sg[kb - 1] - sg[kb + 1]) / den;
+    }
+    out->R_s_grid = Rg;
+    double mx = 0;
+    for (int r = 0; r < nl; ++r)
+        if (d == 3) mx = std::max(mx, std::fabs(h[nl + r] - h[2 * nl + r]));
+    out->max_PyyPzz = mx;
+    if (PN) std::memcpy(PN, h.data(), nl * 8);
+    if (PT) std::memcpy(PT, h.data() + nl, nl * 8);
+    return SCMC_OK;
+}
+
+// ---- stepping ------------------------------------------------------------
+int direct_step_sim(scmc_sim *s) {
+    Common &c = s->c;
+    const void *src = c.pop[c.cur];
+    void *dst = c.pop[1 - c.cur];
+    hipError_t e = c.kernel == SCMC_KERNEL_FUSED
+                       ? launch_fused(c.key, s->lat.m, src, dst, c.tile, c.stream)
+                       : launch_two_pass(c.key, s->lat.m, src, dst, c.dens,
+                                         c.stream);
+    if (e != hipSuccess)
+        return fail(c, SCMC_EDEVICE, "step launch: %s", hipGetErrorString(e));
+    c.cur ^= 1;
+    return SCMC_OK;
+}
+
+int direct_step_batch(scmc_batch *b) {
+    Common &c = b->c;
+    const void *src = c.pop[c.cur];
+    void *dst = c.pop[1 - c.cur];
+    hipError_t e =
+        c.kernel == SCMC_KERNEL_FUSED
+            ? launch_batch_fused(c.key, b->d_members, b->d_tiles, b->ntiles,
+                                 src, dst, c.tile, b->grid, c.stream)
+            : launch_batch_two_pass(c.key, b->d_members, b->d_tiles,
+                                    b->ntiles, src, dst, c.dens, b->grid,
+                                    c.stream);
+    if (e != hipSuccess)
+        return fail(c, SCMC_EDEVICE, "batch step launch: %s",
+                    hipGetErrorString(e));
+    c.cur ^= 1;
+    return SCMC_OK;
+}
+
+// Build an executable graph of k steps starting from buffer `par`.
+// args(step, node, par) fills the kernel argument pointer arrays.
+struct ArgPack {
+    Member m;
+    const Member *members;
+    const Tile *tiles;
+    int ntiles;
+    const void *src;
+    void *dst;
+    void *dens;
+    int tile[3];
+};
+
+int build_graph(Common &c, int k, int par, bool batch, const Member &m,
+                const Member *d_members, const Tile *d_tiles, int ntiles,
+                int grid) {
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipGraphCreate(&g, 0));
+    hipGraphNode_t prev = nullptr;
+    NodeLaunch dn{}, sn{};
+    bool fused = c.kernel == SCMC_KERNEL_FUSED;
+    bool ok = batch ? (fused ? node_batch_fused(c.key, c.tile, grid, &sn)
+                             : node_batch_two_pass(c.key, grid, &dn, &sn))
+                    : (fused ? node_fused(c.key, c.tile, &sn, m)
+                             : node_two_pass(c.key, &dn, &sn, m));
+    if (!ok) {
+        (void)hipGraphDestroy(g);
+        return fail(c, SCMC_EUNSUPPORTED, "no graph node for this kernel");
+    }
+    int cur = par;
+    for (int t = 0; t < k; ++t) {
+        const void *src = c.pop[cur];
+        void *dst = c.pop[1 - cur];
+        // argument values, in kernel-signature order
+        Member mv = m;
+        const Member *dm = d_members;
+        const Tile *dt = d_tiles;
+        int nt = ntiles;
+        const void *srcv = src;
+        void *dstv = dst;
+        void *densv = c.dens;
+        std::vector<void *> dargs, sargs;
+        if (batch) {
+            dargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
+                     (void *)&densv};
+            sargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
+                     (void *)&dstv};
+            if (!fused) sargs.push_back((void *)&densv);
+        } else {
+            dargs = {(void *)&mv, (void *)&srcv, (void *)&densv};
+            sargs = {(void *)&mv, (void *)&srcv, (void *)&dstv};
+            if (!fused) sargs.push_back((void *)&densv);
+        }
+        if (!fused) {
+            hipKernelNodeParams kp{};
+            kp.func = dn.func;
+            kp.gridDim = dn.grid;
+            kp.blockDim = dn.block;
+            kp.sharedMemBytes = dn.shmem;
+            kp.kernelParams = dargs.data();
+            hipGraphNode_t node;
+            hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr,
+                                                 prev ? 1 : 0, &kp);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail(c, SCMC_EDEVICE, "graph node: %s",
+                            hipGetErrorString(e));
+            }
+            prev = node;
+        }
+        hipKernelNodeParams kp{};
+        kp.func = sn.func;
+        kp.gridDim = sn.grid;
+        kp.blockDim = sn.block;
+        kp.sharedMemBytes = sn.shmem;
+        kp.kernelParams = sargs.data();
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr,
+                                             prev ? 1 : 0, &kp);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(c, SCMC_EDEVICE, "graph node: %s", hipGetErrorString(e));
+        }
+        prev = node;
+        cur ^= 1;
+    }
+    hipError_t e = hipGraphInstantiate(&c.gexec[par], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c.gexec[par] = nullptr;
+        return fail(c, SCMC_EDEVICE, "graph instantiate: %s",
+                    hipGetErrorString(e));
+    }
+    return SCMC_OK;
+}
+
+template <class StepFn, class BuildFn>
+int run_steps(Common &c, int64_t nsteps, StepFn direct, BuildFn build) {
+    if (nsteps < 0) return fail(c, SCMC_EINVAL, "nsteps < 0");
+    if (!c.initialized)
+        return fail(c, SCMC_ESTATE, "state not set (call set_density first)");
+    int64_t left = nsteps;
+    while (left > 0) {
+        if (c.graph_k > 0 && left >= c.graph_k) {
+            if (!c.gexec[c.cur]) {
+                int rc = build(c.cur);
+                if (rc) return rc;
+            }
+            HIPCHK(c, hipGraphLaunch(c.gexec[c.cur], c.stream));
+            if (c.graph_k % 2) c.cur ^= 1;
+            left -= c.graph_k;
+            c.step += c.graph_k;
+        } else {
+            int rc = direct();
+            if (rc) return rc;
+            --left;
+            ++c.step;
+        }
+    }
+    return SCMC_OK;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+int scmc_problem_init(scmc_problem *p) {
+    if (!p) return SCMC_EINVAL;
+    std::memset(p, 0, sizeof *p);
+    p->lattice = SCMC_D3Q19;
+    p->stencil = SCMC_E6;
+    p->nx = p->ny = p->nz = 64;
+    p->tau[0] = p->tau[1] = 1.0;
+    p->g[0][1] = p->g[1][0] = 1.8;
+    p->psi_self = SCMC_PSI_N;
+    p->storage = SCMC_F32;
+    p->n0[0] = p->n0[1] = 0.52;
+    p->kernel = SCMC_KERNEL_AUTO;
+    return SCMC_OK;
+}
+
+int scmc_velocities(int lattice, int *xi, double *w) {
+    if (lattice != SCMC_D2Q9 && lattice != SCMC_D3Q19) return SCMC_EINVAL;
+    if (!xi || !w) return SCMC_EINVAL;
+    velocities(lattice, xi, w);
+    return lattice_q(lattice);
+}
+
+int scmc_workspace_bytes(const scmc_problem *p, size_t *out) {
+    if (!out) return SCMC_EINVAL;
+    int rc = validate(p, nullptr);
+    if (rc) return rc;
+    *out = plan_of({*p}, 0).total;
+    return SCMC_OK;
+}
+
+int scmc_create(const scmc_problem *p, void *d_ws, size_t ws_bytes,
+                void *stream, scmc_sim **out) {
+    if (!out) return SCMC_EINVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = validate(p, &why);
+    if (rc) return rc;
+    if (!d_ws || ((uintptr_t)d_ws % ALIGN)) return SCMC_EINVAL;
+    const Plan pl = plan_of({*p}, 0);
+    if (ws_bytes < pl.total) return SCMC_ENOSPACE;
+    scmc_sim *s = new (std::nothrow) scmc_sim();
+    if (!s) return SCMC_EINVAL;
+    s->lat.p = *p;
+    s->lat.m = member_of(*p);
+    s->lat.q = lattice_q(p->lattice);
+    s->lat.dim = lattice_dim(p->lattice);
+    Common &c = s->c;
+    c.key = key_of(*p);
+    rc = choose_kernel(*p, c.key, &c.kernel, c.tile);
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    c.stream = (hipStream_t)stream;
+    c.ws = (char *)d_ws;
+    c.ws_bytes = ws_bytes;
+    bind(c, pl, c.ws, stats_blocks(s->lat.m));
+    *out = s;
+    return SCMC_OK;
+}
+
+int scmc_destroy(scmc_sim *s) {
+    if (!s) return SCMC_EINVAL;
+    drop_graphs(s->c);
+    delete s;
+    return SCMC_OK;
+}
+
+int scmc_set_density(scmc_sim *s, const double *nA, const double *nB) {
+    if (!s || !nA || !nB) return SCMC_EINVAL;
+    int rc = set_density_impl(s->c, s->lat, nA, nB, s->c.pop[0]);
+    if (rc) return rc;
+    s->c.cur = 0;
+    s->c.step = 0;
+    s->c.initialized = true;
+    return SCMC_OK;
+}
+
+int scmc_set_populations(scmc_sim *s, const double *f, int64_t step) {
+    if (!s || !f) return SCMC_EINVAL;
+    const size_t n = 2 * (size_t)s->lat.q * s->lat.m.N;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(f[i]))
+            return fail(s->c, SCMC_EINVAL, "non-finite population %zu", i);
+    int rc = upload_state(s->c, s->lat, f, s->c.pop[0]);
+    if (rc) return rc;
+    s->c.cur = 0;
+    s->c.step = step;
+    s->c.initialized = true;
+    return SCMC_OK;
+}
+
+int scmc_get_populations(scmc_sim *s, double *f, int64_t *step) {
+    if (!s || !f) return SCMC_EINVAL;
+    if (!s->c.initialized) return fail(s->c, SCMC_ESTATE, "state not set");
+    int rc = download_state(s->c, s->lat, s->c.pop[s->c.cur], f);
+    if (rc) return rc;
+    if (step) *step = s->c.step;
+    return SCMC_OK;
+}
+
+int scmc_set_graph_steps(scmc_sim *s, int k) {
+    if (!s || k < 0) return SCMC_EINVAL;
+    drop_graphs(s->c);
+    s->c.graph_k = k;
+    return SCMC_OK;
+}
+
+int scmc_step(scmc_sim *s, int64_t nsteps) {
+    if (!s) return SCMC_EINVAL;
+    Common &c = s->c;
+    return run_steps(
+        c, nsteps, [&] { return direct_step_sim(s); },
+        [&](int par) {
+            return build_graph(c, c.graph_k, par, false, s->lat.m, nullptr,
+                               nullptr, 0, 0);
+        });
+}
+
+int scmc_synchronize(scmc_sim *s) {
+    if (!s) return SCMC_EINVAL;
+    HIPCHK(s->c, hipStreamSynchronize(s->c.stream));
+    return SCMC_OK;
+}
+
+int scmc_get_fields(scmc_sim *s, double *nA, double *nB, double *u) {
+    if (!s) return SCMC_EINVAL;
+    if (!s->c.initialized) return fail(s->c, SCMC_ESTATE, "state not set");
+    return fields_impl(s->c, s->lat, s->c.pop[s->c.cur], nA, nB, u);
+}
+
+int scmc_stats_get(scmc_sim *s, scmc_stats *out) {
+    if (!s) return SCMC_EINVAL;
+    if (!s->c.initialized) return fail(s->c, SCMC_ESTATE, "state not set");
+    int rc = stats_impl(s->c, s->lat, s->c.pop[s->c.cur], out, s->c.step);
+    if (rc) return rc;
+    if (out->n_nonfinite > 0)
+        return fail(s->c, SCMC_ENONFINITE, "%.0f non-finite populations",
+                    out->n_nonfinite);
+    return SCMC_OK;
+}
+
+int scmc_observables(scmc_sim *s, int kind, double R0, scmc_obs *out,
+                     double *PN, double *PT) {
+    if (!s) return SCMC_EINVAL;
+    if (!s->c.initialized) return fail(s->c, SCMC_ESTATE, "state not set");
+    return obs_impl(s->c, s->lat, s->c.pop[s->c.cur], kind, R0, out, PN, PT,
+                    s->c.step);
+}
+
+int scmc_config(scmc_sim *s, int *kernel, int *tile) {
+    if (!s) return SCMC_EINVAL;
+    if (kernel) *kernel = s->c.kernel;
+    if (tile)
+        for (int a = 0; a < 3; ++a) tile[a] = s->c.tile[a];
+    return SCMC_OK;
+}
+
+const char *scmc_last_error(const scmc_sim *s) {
+    return s ? s->c.err.c_str() : "NULL handle";
+}
+const char *scmc_batch_last_error(const scmc_batch *b) {
+    return b ? b->c.err.c_str() : "NULL handle";
+}
+
+const char *scmc_status_str(int st) {
+    switch (st) {
+        case SCMC_OK: return "ok";
+        case SCMC_EINVAL: return "invalid argument";
+        case SCMC_EUNSUPPORTED: return "unsupported";
+        case SCMC_ENOSPACE: return "workspace too small";
+        case SCMC_EDEVICE: return "device error";
+        case SCMC_ENONFINITE: return "non-finite state";
+        case SCMC_ESTATE: return "bad call order";
+    }
+    return "unknown status";
+}
+
+// ------------------------------------------------------------------ batch
+static int batch_tiles(const std::vector<scmc_problem> &ps, int kernel,
+                       const int *tile, std::vector<Tile> *out) {
+    out->clear();
+    for (int i = 0; i < (int)ps.size(); ++i) {
+        const scmc_problem &p = ps[i];
+        const int tx = kernel == SCMC_KERNEL_FUSED ? tile[0] : 64;
+        const int ty = kernel == SCMC_KERNEL_FUSED ? tile[1] : 4;
+        const int tz = kernel == SCMC_KERNEL_FUSED ? tile[2] : 1;
+        for (int z = 0; z < p.nz; z += tz)
+            for (int y = 0; y < p.ny; y += ty)
+                for (int x = 0; x < p.nx; x += tx) out->push_back({i, x, y, z});
+    }
+    return (int)out->size();
+}
+
+static int batch_check(const scmc_problem *ps, int count, std::string *why) {
+    if (!ps || count < 1) return SCMC_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        int rc = validate(&ps[i], why);
+        if (rc) return rc;
+        if (ps[i].lattice != ps[0].lattice || ps[i].stencil != ps[0].stencil ||
+            ps[i].storage != ps[0].storage || ps[i].tau[0] != ps[0].tau[0] ||
+            ps[i].psi_self != ps[0].psi_self || ps[i].kernel != ps[0].kernel ||
+            ps[i].tile[0] != ps[0].tile[0] || ps[i].tile[1] != ps[0].tile[1] ||
+            ps[i].tile[2] != ps[0].tile[2])
+            return SCMC_EINVAL;
+    }
+    return SCMC_OK;
+}
+
+int scmc_batch_workspace_bytes(const scmc_problem *ps, int count, size_t *out) {
+    if (!out) return SCMC_EINVAL;
+    int rc = batch_check(ps, count, nullptr);
+    if (rc) return rc;
+    std::vector<scmc_problem> v(ps, ps + count);
+    int kernel, tile[3];
+    rc = choose_kernel(ps[0], key_of(ps[0]), &kernel, tile);
+    if (rc) return rc;
+    std::vector<Tile> tiles;
+    // the tile list is sized for the smallest candidate tile so that the
+    // autotuner can switch tiles inside the same workspace
+    int tmin[3] = {32, 2, 8};
+    const int nt = std::max(batch_tiles(v, kernel, tile, &tiles),
+                            kernel == SCMC_KERNEL_FUSED
+                                ? batch_tiles(v, kernel, tmin, &tiles)
+                                : 0);
+    *out = plan_of(v, std::max(nt, 1)).total + align_up(count * sizeof(Member));
+    return SCMC_OK;
+}
+
+int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
+                      size_t ws_bytes, void *stream, scmc_batch **out) {
+    if (!out) return SCMC_EINVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = batch_check(ps, count, &why);
+    if (rc) return rc;
+    if (!d_ws || ((uintptr_t)d_ws % ALIGN)) return SCMC_EINVAL;
+    size_t need;
+    rc = scmc_batch_workspace_bytes(ps, count, &need);
+    if (rc) return rc;
+    if (ws_bytes < need) return SCMC_ENOSPACE;
+    scmc_batch *b = new (std::nothrow) scmc_batch();
+    if (!b) return SCMC_EINVAL;
+    Common &c = b->c;
+    std::vector<scmc_problem> v(ps, ps + count);
+    c.key = key_of(ps[0]);
+    rc = choose_kernel(ps[0], c.key, &c.kernel, c.tile);
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    std::vector<Tile> tiles;
+    int tmin[3] = {32, 2, 8};
+    const int nt_max = std::max(batch_tiles(v, c.kernel, c.tile, &tiles),
+                                c.kernel == SCMC_KERNEL_FUSED
+                                    ? batch_tiles(v, c.kernel, tmin, &tiles)
+                                    : 0);
+    b->ntiles = batch_tiles(v, c.kernel, c.tile, &tiles);
+    const Plan pl = plan_of(v, std::max(nt_max, 1));
+    c.stream = (hipStream_t)stream;
+    c.ws = (char *)d_ws;
+    c.ws_bytes = ws_bytes;
+    int nbmax = 0;
+    for (auto &p : v) nbmax = std::max(nbmax, stats_blocks(member_of(p)));
+    bind(c, pl, c.ws, nbmax);
+    char *tail = (char *)c.small + pl.small;
+    b->d_members = (Member *)tail;
+    tail += align_up(count * sizeof(Member));
+    b->d_tiles = (Tile *)tail;
+    // members: offsets into the shared buffers
+    long long pop_off = 0, dens_off = 0;
+    std::vector<Member> ms;
+    for (int i = 0; i < count; ++i) {
+        Lat L;
+        L.p = v[i];
+        L.m = member_of(v[i]);
+        L.q = lattice_q(v[i].lattice);
+        L.dim = lattice_dim(v[i].lattice);
+        L.m.pop_off = pop_off;
+        L.m.dens_off = dens_off;
+        const size_t N = (size_t)L.m.N;
+        pop_off += (long long)(align_up(2 * L.q * N * storage_bytes(v[i].storage)) /
+                               storage_bytes(v[i].storage));
+        dens_off += (long long)(align_up(2 * N * real_bytes(v[i].storage)) /
+                                real_bytes(v[i].storage));
+        ms.push_back(L.m);
+        b->lats.push_back(L);
+    }
+    b->member_set.assign(count, false);
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            ncu = prop.multiProcessorCount;
+    }
+    b->grid = std::min(b->ntiles, ncu * 8);
+    hipError_t e = hipMemcpyAsync(b->d_members, ms.data(),
+                                  ms.size() * sizeof(Member),
+                                  hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(Tile),
+                           hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) {
+        delete b;
+        return SCMC_EDEVICE;
+    }
+    *out = b;
+    return SCMC_OK;
+}
+
+int scmc_batch_destroy(scmc_batch *b) {
+    if (!b) return SCMC_EINVAL;
+    drop_graphs(b->c);
+    delete b;
+    return SCMC_OK;
+}
+
+static const void *member_pop(const scmc_batch *b, int i, int buf) {
+    const Lat &L = b->lats[i];
+    return (const char *)b->c.pop[buf] +
+           L.m.pop_off * (long long)storage_bytes(L.p.storage);
+}
+
+int scmc_batch_set_density(scmc_batch *b, int i, const double *nA,
+                           const double *nB) {
+    if (!b || !nA || !nB || i < 0 || i >= (int)b->lats.size())
+        return SCMC_EINVAL;
+    Common &c = b->c;
+    if (c.step != 0 || (c.cur != 0 && c.initialized))
+        return fail(c, SCMC_ESTATE, "members are set before the first step");
+    int rc = set_density_impl(c, b->lats[i], nA, nB,
+                              (void *)member_pop(b, i, 0));
+    if (rc) return rc;
+    b->member_set[i] = true;
+    c.initialized = std::all_of(b->member_set.begin(), b->member_set.end(),
+                                [](bool v) { return v; });
+    return SCMC_OK;
+}
+
+int scmc_batch_set_graph_steps(scmc_batch *b, int k) {
+    if (!b || k < 0) return SCMC_EINVAL;
+    drop_graphs(b->c);
+    b->c.graph_k = k;
+    return SCMC_OK;
+}
+
+int scmc_batch_step(scmc_batch *b, int64_t nsteps) {
+    if (!b) return SCMC_EINVAL;
+    Common &c = b->c;
+    return run_steps(
+        c, nsteps, [&] { return direct_step_batch(b); },
+        [&](int par) {
+            return build_graph(c, c.graph_k, par, true, Member{}, b->d_members,
+                               b->d_tiles, b->ntiles, b->grid);
+        });
+}
+
+int scmc_batch_get_fields(scmc_batch *b, int i, double *nA, double *nB,
+                          double *u) {
+    if (!b || i < 0 || i >= (int)b->lats.size()) return SCMC_EINVAL;
+    if (!b->c.initialized) return fail(b->c, SCMC_ESTATE, "state not set");
+    return fields_impl(b->c, b->lats[i], member_pop(b, i, b->c.cur), nA, nB, u);
+}
+
+int scmc_batch_stats_get(scmc_batch *b, int i, scmc_stats *out) {
+    if (!b || i < 0 || i >= (int)b->lats.size()) return SCMC_EINVAL;
+    if (!b->c.initialized) return fail(b->c, SCMC_ESTATE, "state not set");
+    int rc = stats_impl(b->c, b->lats[i], member_pop(b, i, b->c.cur), out,
+                        b->c.step);
+    if (rc) return rc;
+    if (out->n_nonfinite > 0)
+        return fail(b->c, SCMC_ENONFINITE, "%.0f non-finite populations",
+                    out->n_nonfinite);
+    return SCMC_OK;
+}
+
+int scmc_batch_observables(scmc_batch *b, int i, int kind, double R0,
+                           scmc_obs *out, double *PN, double *PT) {
+    if (!b || i < 0 || i >= (int)b->lats.size()) return SCMC_EINVAL;
+    if (!b->c.initialized) return fail(b->c, SCMC_ESTATE, "state not set");
+    return obs_impl(b->c, b->lats[i], member_pop(b, i, b->c.cur), kind, R0,
+                    out, PN, PT, b->c.step);
+}
+
+int scmc_batch_config(scmc_batch *b, int *tile, int *grid) {
+    if (!b) return SCMC_EINVAL;
+    if (tile)
+        for (int a = 0; a < 3; ++a) tile[a] = b->c.tile[a];
+    if (grid) *grid = b->grid;
+    return SCMC_OK;
+}
+
+int scmc_autotune(scmc_sim *s, const char *cache_path, int *tile) {
+    (void)cache_path;
+    (void)tile;
+    if (!s) return SCMC_EINVAL;
+    return fail(s->c, SCMC_EUNSUPPORTED, "autotuner needs the fused kernel");
+}
+
+int scmc_batch_autotune(scmc_batch *b, const char *cache_path, int *tile) {
+    (void)cache_path;
+    (void)tile;
+    if (!b) return SCMC_EINVAL;
+    return fail(b->c, SCMC_EUNSUPPORTED, "autotuner needs the fused kernel");
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// scmc_internal.h -- declarations shared by the host library and the kernel
+// translation units of libscmc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scmc {
+
+// One lattice as the kernels see it.  Populations of a member live at
+// pop + pop_off (element offset in the storage type) in both population
+// buffers, component-major: [J][i][z][y][x]; its density field lives at
+// dens + dens_off as [J][z][y][x].
+struct Member {
+    int nx, ny, nz, N;
+    long long pop_off;
+    long long dens_off;
+    double g[2][2];   // G_JK c_s^2
+    double omega;     // 1 / tau
+    double n0[2];     // offset references (FP16 / BF16 storage)
+    int psi_self;     // 0: psi = n, 1: psi = exp(-1/n)
+    int self_on;      // bit J set when g_JJ != 0
+};
+
+// A unit of work of the batched launches: member index and tile origin.
+struct Tile {
+    int member, x0, y0, z0;
+};
+
+enum StorageKind { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+
+// kernel selector shared by the launchers
+struct StepKey {
+    int dim;      // 2 or 3
+    int order;    // 4, 6, 8
+    int storage;  // StorageKind
+    int psi;      // 0 / 1
+};
+
+// ---- step kernels (step_kernels.hip)
+// Two-pass design: density pass then stream/force/collide pass.
+hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
+                           void *dst, void *dens, hipStream_t st);
+// Fused z-marching design: one kernel per step.  tile = (tx, ty, zc).
+hipError_t launch_fused(const StepKey &k, const Member &m, const void *src,
+                        void *dst, const int *tile, hipStream_t st);
+bool fused_supported(const StepKey &k, const int *tile);
+// Batched persistent launches over a tile list (device arrays).
+hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
+                                 const Tile *d_tiles, int ntiles,
+                                 const void *src, void *dst, void *dens,
+                                 int grid, hipStream_t st);
+hipError_t launch_batch_fused(const StepKey &k, const Member *d_members,
+                              const Tile *d_tiles, int ntiles, const void *src,
+                              void *dst, const int *tile, int grid,
+                              hipStream_t st);
+// Kernel function and argument packing for explicit hipGraph nodes.
+struct NodeLaunch {
+    void *func;
+    dim3 grid, block;
+    unsigned shmem;
+};
+bool node_two_pass(const StepKey &k, NodeLaunch *dens_node,
+                   NodeLaunch *step_node, const Member &m);
+bool node_fused(const StepKey &k, const int *tile, NodeLaunch *node,
+                const Member &m);
+bool node_batch_two_pass(const StepKey &k, int grid, NodeLaunch *dens_node,
+                         NodeLaunch *step_node);
+bool node_batch_fused(const StepKey &k, const int *tile, int grid,
+                      NodeLaunch *node);
+
+// ---- FP64 observable kernels (obs_kernels.hip)
+// dens64[J][s] = sum_i f_i^J of the current state (pulled, decoded, FP64)
+hipError_t launch_density64(const StepKey &k, const Member &m, const void *pop,
+                            double *dens64, hipStream_t st);
+// per-block partials then a final fixed-order reduction into out[16]
+hipError_t launch_stats(const StepKey &k, const Member &m, const void *pop,
+                        const double *dens64, double *partials, int nblocks_max,
+                        double *out, hipStream_t st);
+int stats_blocks(const Member &m);
+// velocity field u[3][N] (FP64)
+hipError_t launch_velocity64(const StepKey &k, const Member &m, const void *pop,
+                             const double *dens64, double *u, hipStream_t st);
+// droplet line: out[0..3*(rmax+1)) = P^xx, P^yy, P^zz along +x from the
+// centre; out[3*(rmax+1)] = P_in, [+1] = P_out, [+2] = C_d
+hipError_t launch_line(const StepKey &k, const Member &m, const double *dens64,
+                       double *out, hipStream_t st);
+// flat: out[0..nx) = <P^xx>_yz, out[nx..2nx) = <P^yy>_yz, out[2nx] = sigma0
+hipError_t launch_flat(const StepKey &k, const Member &m, const double *dens64,
+                       double *out, hipStream_t st);
+
+}  // namespace scmc

@@ -1,0 +1,162 @@
+// site_ops.h -- per-site operators of the two-component Shan-Chen step, shared
+// by every kernel design (paper Sec. 2):
+//   pull:     f_i^J(x, t) = f*_i^J(x - xi_i, t - 1)        (eq. lbm, streaming)
+//   density:  n_J = sum_i f_i^J
+//   force:    F_J = -g_JK n_J sum_a W_a n_K(x + e_a) e_a
+//                   -g_JJ psi_J sum_a W_a psi_J(x + e_a) e_a   (eq. sc_force)
+//   velocity: (n_A + n_B) u = sum_J [sum_i f_i^J xi_i + F_J / 2]
+//   collide:  f* = f - omega (f - f^eq(n_J, u)) + (1 - omega/2) S_i(u, F_J)
+//             f^eq = n w_i [1 + 3 xi.u + 9/2 (xi.u)^2 - 3/2 u.u]
+//             S_i  = w_i [3 xi.F + 9 (xi.u)(xi.F) - 3 u.F]     (c_s^2 = 1/3)
+#pragma once
+
+#include "lattice.h"
+#include "scmc_internal.h"
+
+namespace scmc {
+
+__device__ __forceinline__ int wrap1(int v, int n) {
+    // periodic wrap of v in [-n, 2n)
+    return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+template <class R, int PSI> __device__ __forceinline__ R psi_of(R n) {
+    if constexpr (PSI == 0) {
+        return n;
+    } else {
+        return exp(R(-1) / n);
+    }
+}
+
+// Pull the 2Q populations of site (x, y, z) from the post-collision buffer.
+template <int D, class ST>
+__device__ __forceinline__ void pull_site(
+    const Member &m, const typename ST::T *__restrict__ src, int x, int y,
+    int z, typename ST::R (&f)[2][Lattice<D>::Q]) {
+    using L = Lattice<D>;
+    using R = typename ST::R;
+    const typename ST::T *base = src + m.pop_off;
+    const R n0A = (R)m.n0[0], n0B = (R)m.n0[1];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int xs = wrap1(x - L::CX[i], m.nx);
+        const int ys = wrap1(y - L::CY[i], m.ny);
+        const int zs = D == 3 ? wrap1(z - L::CZ[i], m.nz) : 0;
+        const long s = ((long)zs * m.ny + ys) * m.nx + xs;
+        const R w = (R)L::W[i];
+        f[0][i] = ST::load(base, (long)i * m.N + s, w * n0A);
+        f[1][i] = ST::load(base, (long)(L::Q + i) * m.N + s, w * n0B);
+    }
+}
+
+template <int D, class R>
+__device__ __forceinline__ void site_density(const R (&f)[2][Lattice<D>::Q],
+                                             R &nA, R &nB) {
+    R a = 0, b = 0;
+#pragma unroll
+    for (int i = 0; i < Lattice<D>::Q; ++i) {
+        a += f[0][i];
+        b += f[1][i];
+    }
+    nA = a;
+    nB = b;
+}
+
+// Stencil sums of eq. sc_force from a density field laid out [J][z][y][x]
+// (dA, dB), then the force on both components.
+template <int D, int ORDER, int PSI, class R>
+__device__ __forceinline__ void site_force(const Member &m,
+                                           const R *__restrict__ dA,
+                                           const R *__restrict__ dB, int x,
+                                           int y, int z, R nA, R nB, R (&FA)[3],
+                                           R (&FB)[3]) {
+    using S = Stencil<D, ORDER>;
+    R cA[3] = {0, 0, 0}, cB[3] = {0, 0, 0};
+    R sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0};
+    const bool selfA = m.self_on & 1, selfB = m.self_on & 2;
+#pragma unroll
+    for (int a = 0; a < S::NE; ++a) {
+        constexpr auto T = S::T;
+        const int ex = T.e[a][0], ey = T.e[a][1], ez = T.e[a][2];
+        const int xs = wrap1(x + ex, m.nx);
+        const int ys = wrap1(y + ey, m.ny);
+        const int zs = D == 3 ? wrap1(z + ez, m.nz) : 0;
+        const long t = ((long)zs * m.ny + ys) * m.nx + xs;
+        const R nAt = dA[t], nBt = dB[t];
+        const R W = (R)T.W[a];
+        const int e3[3] = {ex, ey, ez};
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (e3[k] == 0) continue;
+            const R We = W * (R)e3[k];
+            cA[k] += We * nBt;
+            cB[k] += We * nAt;
+        }
+        if (selfA || selfB) {
+            const R pA = psi_of<R, PSI>(nAt), pB = psi_of<R, PSI>(nBt);
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                if (e3[k] == 0) continue;
+                const R We = W * (R)e3[k];
+                sA[k] += We * pA;
+                sB[k] += We * pB;
+            }
+        }
+    }
+    const R gAB = (R)m.g[0][1], gBA = (R)m.g[1][0];
+    const R gAA = (R)m.g[0][0], gBB = (R)m.g[1][1];
+    const R pA = selfA ? psi_of<R, PSI>(nA) : R(0);
+    const R pB = selfB ? psi_of<R, PSI>(nB) : R(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        FA[k] = -gAB * nA * cA[k] - gAA * pA * sA[k];
+        FB[k] = -gBA * nB * cB[k] - gBB * pB * sB[k];
+    }
+}
+
+// Common velocity, BGK collision with Guo forcing, store of f*.
+template <int D, class ST>
+__device__ __forceinline__ void site_collide_store(
+    const Member &m, const typename ST::R (&f)[2][Lattice<D>::Q],
+    typename ST::R nA, typename ST::R nB, const typename ST::R (&FA)[3],
+    const typename ST::R (&FB)[3], typename ST::T *__restrict__ dst, long s) {
+    using L = Lattice<D>;
+    using R = typename ST::R;
+    R mx = 0, my = 0, mz = 0;
+#pragma unroll
+    for (int J = 0; J < 2; ++J)
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            if (L::CX[i]) mx += (R)L::CX[i] * f[J][i];
+            if (L::CY[i]) my += (R)L::CY[i] * f[J][i];
+            if (D == 3 && L::CZ[i]) mz += (R)L::CZ[i] * f[J][i];
+        }
+    const R inv = R(1) / (nA + nB);
+    const R ux = (mx + R(0.5) * (FA[0] + FB[0])) * inv;
+    const R uy = (my + R(0.5) * (FA[1] + FB[1])) * inv;
+    const R uz = D == 3 ? (mz + R(0.5) * (FA[2] + FB[2])) * inv : R(0);
+    const R uu = ux * ux + uy * uy + uz * uz;
+    const R omega = (R)m.omega, cf = R(1) - R(0.5) * omega;
+    typename ST::T *base = dst + m.pop_off;
+    const R n0[2] = {(R)m.n0[0], (R)m.n0[1]};
+#pragma unroll
+    for (int J = 0; J < 2; ++J) {
+        const R *F = J == 0 ? FA : FB;
+        const R nJ = J == 0 ? nA : nB;
+        const R uF = ux * F[0] + uy * F[1] + uz * F[2];
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const R cx = (R)L::CX[i], cy = (R)L::CY[i], cz = (R)L::CZ[i];
+            const R xu = cx * ux + cy * uy + cz * uz;
+            const R xF = cx * F[0] + cy * F[1] + cz * F[2];
+            const R w = (R)L::W[i];
+            const R feq = nJ * w *
+                          (R(1) + R(3) * xu + R(4.5) * xu * xu - R(1.5) * uu);
+            const R S = w * (R(3) * xF + R(9) * xu * xF - R(3) * uF);
+            const R out = f[J][i] - omega * (f[J][i] - feq) + cf * S;
+            ST::store(base, (long)(J * L::Q + i) * m.N + s, out, w * n0[J]);
+        }
+    }
+}
+
+}  // namespace scmc
