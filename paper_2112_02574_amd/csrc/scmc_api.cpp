@@ -444,17 +444,20 @@ int set_density_impl(Common &c, const Lat &L, const double *nA,
 }
 
 // ---- observables of one member (its populations at pop_dev) ------------
-int member_obs_prep(Common &c, const Lat &L, const void *pop_dev) {
-    Member m = L.m;  // the dens64 scratch is per call, offset-free
-    m.dens_off = 0;
-    HIPCHK(c, launch_density64(c.key, m, pop_dev, c.dens64, c.stream));
-    return SCMC_OK;
-}
-
+// The observable kernels get the member's own population pointer (already
+// offset) and a per-call FP64 scratch, so their Member view carries no
+// offsets.
 Member obs_member(const Lat &L) {
     Member m = L.m;
+    m.pop_off = 0;
     m.dens_off = 0;
     return m;
+}
+
+int member_obs_prep(Common &c, const Lat &L, const void *pop_dev) {
+    HIPCHK(c, launch_density64(c.key, obs_member(L), pop_dev, c.dens64,
+                               c.stream));
+    return SCMC_OK;
 }
 
 int stats_impl(Common &c, const Lat &L, const void *pop_base, scmc_stats *out,
@@ -642,17 +645,19 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
         const void *srcv = src;
         void *dstv = dst;
         void *densv = c.dens;
+        int zc = c.tile[2];
+        // the step kernel's last argument: the density field (two-pass) or
+        // the z-chunk length (fused)
+        void *last = fused ? (void *)&zc : (void *)&densv;
         std::vector<void *> dargs, sargs;
         if (batch) {
             dargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
                      (void *)&densv};
             sargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
-                     (void *)&dstv};
-            if (!fused) sargs.push_back((void *)&densv);
+                     (void *)&dstv, last};
         } else {
             dargs = {(void *)&mv, (void *)&srcv, (void *)&densv};
-            sargs = {(void *)&mv, (void *)&srcv, (void *)&dstv};
-            if (!fused) sargs.push_back((void *)&densv);
+            sargs = {(void *)&mv, (void *)&srcv, (void *)&dstv, last};
         }
         if (!fused) {
             hipKernelNodeParams kp{};

@@ -81,9 +81,18 @@ def test_populations_match_oracle(case, storage, tol, steps, kernel):
     assert np.abs(u - o.velocity()).max() < tol * 10
     st, so = sim.scmc_stats_get(), o.stats()
     np.testing.assert_allclose(st["mass"], so["mass"], rtol=1e-12 if storage == scmc.F64 else 1e-6)
-    assert np.abs(st["momentum"] - so["momentum"]).max() < (1e-11 if storage == scmc.F64 else 1e-4)
+    if storage == scmc.F64:
+        assert np.abs(st["momentum"] - so["momentum"]).max() < 1e-11
     np.testing.assert_allclose(st["min_n"], so["min_n"], atol=tol * 10)
     assert abs(st["max_u"] - so["max_u"]) < tol * 10
+    # the FP64 reductions against the oracle's statistics of the very same
+    # (GPU-produced) state: FP32 storage breaks exact conservation by its
+    # rounding, so momentum is compared state for state
+    o.set_populations(f[:, np.argsort(_perm(lattice, dim))].reshape(o.f.shape))
+    so2 = o.stats()
+    np.testing.assert_allclose(st["mass"], so2["mass"], rtol=1e-13)
+    assert np.abs(st["momentum"] - so2["momentum"]).max() < 1e-10
+    assert abs(st["max_u"] - so2["max_u"]) < 1e-12
     sim.close()
 
 
@@ -118,11 +127,12 @@ def test_stats_and_observables_match_oracle_fp64():
     p = scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), g=g, storage=scmc.F64)
     sim = scmc.Sim(p)
     sim.scmc_set_density(nA, nB)
-    sim.scmc_step(50)
+    sim.scmc_step(400)
     o = O.Oracle(3, 6, (L, L, L), g=g)
     o.set_density(nA, nB)
-    o.run(50)
+    o.run(400)
     ob, oo = sim.scmc_observables(scmc.OBS_DROPLET, R0), o.droplet_observables(R0)
+    assert oo["dP"] > 0 and oo["C_d"] > 0  # a settled droplet
     for k in ("P_in", "P_out", "dP", "C_d", "R_s", "R_s_grid", "sigma_s"):
         assert abs(ob[k] - oo[k]) < 1e-10 * max(1.0, abs(oo[k])), (k, ob[k], oo[k])
     assert np.abs(ob["PN"] - oo["PN"]).max() < 1e-12
@@ -194,7 +204,7 @@ def test_deterministic_reductions():
 def test_graph_replay_matches_direct_launches():
     shape = (12, 20, 36)
     nA, nB = _random_state(shape, 9)
-    p = scmc.problem(scmc.D3Q19, scmc.E6, shape, storage=scmc.F32)
+    p = scmc.problem(scmc.D3Q19, scmc.E6, shape, g=((-0.1, 1.4), (1.4, 0.05)), storage=scmc.F32)
     a = scmc.Sim(p)
     a.scmc_set_density(nA, nB)
     a.scmc_step(23)
@@ -207,6 +217,7 @@ def test_graph_replay_matches_direct_launches():
         b.scmc_synchronize()
     fb, st = b.scmc_get_populations()
     assert st == 23
+    assert np.isfinite(fa).all()
     assert np.array_equal(fa, fb)
 
 
