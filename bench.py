@@ -1,0 +1,271 @@
+"""Throughput benchmark of the two-component Shan-Chen step on one MI355X.
+
+Workload: D3Q19 droplet on a 128^3 periodic box, R0 = 24, tau = 1,
+g_AB = G c_s^2 = 1.8 (symmetric, psi = n), E6 force stencil, populations
+stored and updated in FP32 (structure-of-arrays), synthetic tanh initial
+profile of Sec. 4.  A timed step is one lattice update of both components
+(stream + concentrations + Shan-Chen force + common velocity + BGK/Guo
+collide); the FP64 statistics and the pressure-tensor / sigma[R] / R_s
+reductions run at the paper's monitoring cadence (every 2^11 steps, Sec. 4)
+and at least once inside the timed region.
+
+Prints one JSON line: MLUPS (million lattice-site updates per second, both
+components), the roofline of the step kernel (algorithmic bytes 4 Q s per
+site = 304 B for FP32 over the event-timed kernel time, against the 8 TB/s
+HBM peak), the HBM traffic measured by rocprofv3 counters for the same
+kernel source when available, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+OBS_EVERY = 2048
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "fused_e6_f32_128cube_traffic.txt")
+TRACE_MD = os.path.join(ROOT, "profiles", "fused_e6_f32_128cube_kernel_trace.md")
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace "
+             "-o trace -- python3 bench.py --steps 300 --warmup 20 --cpu-steps 0",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch "
+             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write "
+             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0",
+    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_copy_fetch "
+                  "-o cfetch -- python3 bench.py --copy-calib 1024",
+    "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_copy_write "
+                  "-o cwrite -- python3 bench.py --copy-calib 1024",
+}
+KERNEL_SOURCES = ["paper_2112_02574_amd/csrc/fused_kernels.hip",
+                  "paper_2112_02574_amd/csrc/site_ops.h",
+                  "paper_2112_02574_amd/csrc/lattice.h"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_sites):
+    """HBM bytes per step launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("sites") != n_sites:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def _finite(v):
+    return v if isinstance(v, (int, float)) and v == v and abs(v) != float("inf") else None
+
+
+def summarize_profiles(outdir, L=128):
+    """Write the profiles/ summaries from the rocprofv3 CSV output of the
+    commands in PROFILE_COMMANDS (run from the repository root)."""
+    import csv
+
+    def rows(sub, suffix):
+        d = os.path.join(outdir, sub)
+        name = [f for f in os.listdir(d) if f.endswith(suffix)][0]
+        return list(csv.DictReader(open(os.path.join(d, name))))
+
+    def mean_counter(sub, prefix):
+        v = [float(r["Counter_Value"]) for r in rows(sub, "_counter_collection.csv")
+             if r["Kernel_Name"].startswith(prefix)]
+        return sum(v) / len(v), len(v)
+
+    stats = rows("prof_trace", "_kernel_stats.csv")
+    top = stats[0]["Name"]
+    prefix = top.split("(")[0]
+    fetch, nf = mean_counter("prof_fetch", prefix)
+    write, nw = mean_counter("prof_write", prefix)
+    cf, _ = mean_counter("prof_copy_fetch", "__amd_rocclr_copyBuffer")
+    cw, _ = mean_counter("prof_copy_write", "__amd_rocclr_copyBuffer")
+    copy_bytes = 1024 * (1 << 20)
+    sf, sw = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    N = L ** 3
+    hbm = fetch * 1024 * sf + write * 1024 * sw
+    traffic = {"kernel": top, "sites": N, "dispatches": {"fetch": nf, "write": nw},
+               "fetch_size_kib_per_dispatch": round(fetch, 1),
+               "write_size_kib_per_dispatch": round(write, 1),
+               "copy_calibration": {"bytes": copy_bytes, "fetch_size_kib": round(cf, 1),
+                                    "write_size_kib": round(cw, 1), "fetch_scale": round(sf, 4),
+                                    "write_scale": round(sw, 4)},
+               "hbm_bytes_per_launch": round(hbm), "algorithmic_bytes_per_launch": 304 * N,
+               "ratio_to_algorithmic": round(hbm / (304 * N), 4),
+               "kernel_source_hash": kernel_source_hash(),
+               "commands": [PROFILE_COMMANDS[k] for k in ("fetch", "write", "copy_fetch", "copy_write")]}
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(traffic, fh, indent=1)
+        fh.write("\n")
+    lines = ["# Kernel trace: D3Q19 E6 droplet 128^3, FP32 populations", "",
+             "Command (repository root, one MI355X):", "", "    " + PROFILE_COMMANDS["trace"], "",
+             "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in stats[:8]:
+        lines.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f |" % (
+            r["Name"].split("(")[0], r["Calls"], float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    avg_us = float(stats[0]["AverageNs"]) / 1e3
+    lines += ["", "Dominant kernel: %.1f us per step = %.0f MLUPS; algorithmic %d B/site -> %.0f GB/s "
+              "(%.1f%% of 8 TB/s)." % (avg_us, N / avg_us, 304, 304 * N / avg_us / 1e3,
+                                       304 * N / avg_us / 1e3 / 80),
+              "", "HBM traffic (rocprofv3 counters, scaled by a 1 GiB copy): FETCH_SIZE %.0f KiB x %.3f "
+              "+ WRITE_SIZE %.0f KiB x %.3f = %.1f MB per launch, %.3f x the algorithmic %.1f MB." % (
+                  fetch, sf, write, sw, hbm / 1e6, hbm / (304 * N), 304 * N / 1e6), ""]
+    with open(TRACE_MD, "w") as fh:
+        fh.write("\n".join(lines))
+    print(open(TRACE_MD).read())
+
+
+def cpu_baseline(L, R0, steps):
+    """The FP64 oracle on the same workload, a bounded number of steps."""
+    from oracle import oracle as O
+    from paper_2112_02574_amd import inputs
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = O.Oracle(3, 6, (L, L, L), tau=1.0, g=((0.0, 1.8), (1.8, 0.0)), nthreads=threads)
+    o.set_density(*inputs.droplet(L, L, L, R=R0))
+    o.run(1)  # first touch of the work arrays
+    t0 = time.perf_counter()
+    o.run(steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(L ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"FP64 oracle, {steps} steps of the same {L}^3 D3Q19/E6 droplet "
+                      f"({L ** 3 * steps:.3g} site updates, {dt:.1f} s)"}
+
+
+def run(args):
+    import torch
+
+    from paper_2112_02574_amd import inputs
+    from paper_2112_02574_amd import scmc
+
+    L, R0 = args.size, args.size * 24.0 / 128.0
+    N = L ** 3
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    p = scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), tau=1.0, g=((0.0, 1.8), (1.8, 0.0)),
+                     storage=scmc.F32, kernel=scmc.KERNEL_AUTO,
+                     tile=tuple(args.tile) if args.tile else (0, 0, 0))
+    sim = scmc.Sim(p, device=dev, stream=stream)
+    if args.graph:
+        sim.scmc_set_graph_steps(args.graph)
+    sim.scmc_set_density(*inputs.droplet(L, L, L, R=R0))
+    kernel, tile = sim.scmc_config()
+
+    sim.scmc_step(args.warmup)
+    sim.scmc_synchronize()
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    step_ms = 0.0
+    obs = stats = None
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.steps:
+        chunk = min(OBS_EVERY, args.steps - done)
+        ev0.record(stream)
+        sim.scmc_step(chunk)
+        ev1.record(stream)
+        ev1.synchronize()
+        step_ms += ev0.elapsed_time(ev1)
+        done += chunk
+        # monitoring reductions (FP64): statistics, pressure tensor, sigma[R], R_s
+        stats = sim.scmc_stats_get()
+        obs = sim.scmc_observables(scmc.OBS_DROPLET, R0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    ms_per_step = wall * 1e3 / args.steps
+    mlups = N * args.steps / wall / 1e6
+    kernel_ms = step_ms / args.steps
+    bytes_alg = 4 * 19 * 4 * N  # read + write of 2 x 19 FP32 populations
+    achieved = bytes_alg / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(N)
+    line = {
+        "metric": "MLUPS (2-component D3Q19 Shan-Chen step)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded tanh droplet, no dataset)",
+        "config": {"workload": f"D3Q19 E6 droplet {L}^3 R0={R0:g} tau=1 g_AB=1.8 psi=n FP32 SoA",
+                   "sites": N, "kernel": {1: "two_pass", 2: "fused"}[kernel],
+                   "tile": list(tile), "graph_steps": args.graph,
+                   "reductions_every": OBS_EVERY, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel_ms": round(kernel_ms, 5),
+                     "bytes_per_site": 4 * 19 * 4},
+        "observables": {"dP": _finite(obs["dP"]), "R_s": _finite(obs["R_s"]),
+                        "sigma_s": _finite(obs["sigma_s"]), "step": obs["step"],
+                        "mass": stats["mass"].tolist(), "max_u": _finite(stats["max_u"])},
+    }
+    sim.close()
+    if args.cpu_steps > 0:
+        line["cpu_baseline"] = cpu_baseline(L, R0, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--graph", type=int, default=0,
+                    help="steps per captured hipGraph (0: direct launches)")
+    ap.add_argument("--tile", type=int, nargs=3, default=None)
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="oracle steps of the CPU baseline (0 to skip)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (torch copy_), the "
+                         "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--summarize", metavar="DIR", default=None,
+                    help="only write the profiles/ summaries from rocprofv3 output in DIR")
+    args = ap.parse_args()
+    if args.summarize:
+        summarize_profiles(args.summarize, args.size)
+        return
+    if args.copy_calib:
+        import torch
+        n = args.copy_calib * (1 << 20)
+        a = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": n, "launches": 5}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding "
+              "(sweep members or z-slabs per GPU) is not part of this library", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py is single-process, single-GPU", file=sys.stderr)
+        sys.exit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()
