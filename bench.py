@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNELS = {"auto": 0, "two_pass": 1, "fused": 2, "fused_repull": 3, "fused_pipe": 4}
+KERNEL_NAMES = {0: "auto", 1: "two_pass", 2: "fused", 3: "fused_repull", 4: "fused_pipe"}
 OBS_EVERY = 2048
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "fused_e6_f32_128cube_traffic.txt")
 TRACE_MD = os.path.join(ROOT, "profiles", "fused_e6_f32_128cube_kernel_trace.md")
@@ -158,9 +160,11 @@ def run(args):
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     p = scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), tau=1.0, g=((0.0, 1.8), (1.8, 0.0)),
-                     storage=scmc.F32, kernel=scmc.KERNEL_AUTO,
+                     storage=scmc.F32, kernel=KERNELS[args.kernel],
                      tile=tuple(args.tile) if args.tile else (0, 0, 0))
     sim = scmc.Sim(p, device=dev, stream=stream)
+    if args.tile is None and args.kernel == "auto":
+        sim.scmc_autotune(args.tune_cache)   # picks design and tile on this GPU
     if args.graph:
         sim.scmc_set_graph_steps(args.graph)
     sim.scmc_set_density(*inputs.droplet(L, L, L, R=R0))
@@ -210,7 +214,7 @@ def run(args):
         "dtype": "f32",
         "data": "synthetic (seeded tanh droplet, no dataset)",
         "config": {"workload": f"D3Q19 E6 droplet {L}^3 R0={R0:g} tau=1 g_AB=1.8 psi=n FP32 SoA",
-                   "sites": N, "kernel": {1: "two_pass", 2: "fused"}[kernel],
+                   "sites": N, "kernel": KERNEL_NAMES[kernel],
                    "tile": list(tile), "graph_steps": args.graph,
                    "reductions_every": OBS_EVERY, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -236,6 +240,9 @@ def main():
     ap.add_argument("--graph", type=int, default=0,
                     help="steps per captured hipGraph (0: direct launches)")
     ap.add_argument("--tile", type=int, nargs=3, default=None)
+    ap.add_argument("--kernel", choices=sorted(KERNELS), default="auto")
+    ap.add_argument("--tune-cache", default=os.path.join(os.environ.get("TMPDIR", "/tmp"),
+                                                         "scmc_autotune.txt"))
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps of the CPU baseline (0 to skip)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",

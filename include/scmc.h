@@ -71,10 +71,16 @@ typedef enum {
     SCMC_BF16_OFF = 3 /* same with bfloat16 */
 } scmc_storage;
 typedef enum {
-    SCMC_KERNEL_AUTO = 0,     /* fused when available, else two-pass */
-    SCMC_KERNEL_TWO_PASS = 1, /* density pass + stream/force/collide pass */
-    SCMC_KERNEL_FUSED = 2     /* one z-marching kernel per step (D3Q19 with
-                                 E4/E6; D2Q9 with E4/E6/E8) */
+    SCMC_KERNEL_AUTO = 0,        /* fused when available, else two-pass */
+    SCMC_KERNEL_TWO_PASS = 1,    /* density pass + stream/force/collide pass */
+    SCMC_KERNEL_FUSED = 2,       /* one z-marching kernel per step (D3Q19 with
+                                    E4/E6, FP32/FP16/BF16 storage); the pulled
+                                    populations wait in registers */
+    SCMC_KERNEL_FUSED_REPULL = 3, /* same, but the populations of the
+                                     collided plane are pulled again (from
+                                     cache) instead of held in registers */
+    SCMC_KERNEL_FUSED_PIPE = 4    /* fused, with the next plane's loads issued
+                                     before the current plane's collision */
 } scmc_kernel;
 typedef enum { SCMC_OBS_FLAT = 0, SCMC_OBS_DROPLET = 1 } scmc_obs_kind;
 
@@ -164,6 +170,23 @@ int scmc_stats_get(scmc_sim *s, scmc_stats *out);
  * the sigma[R] scan (DROPLET). */
 int scmc_observables(scmc_sim *s, int kind, double R0, scmc_obs *out,
                      double *PN, double *PT);
+
+/* Flat-interface steady state (Sec. 4: the droplet runs start from the bulk
+ * concentrations of a converged flat interface).  Runs the problem's lattice,
+ * stencil, couplings, tau, psi and storage on a transverse-thin periodic box
+ * of lx x 5 (x 5 in 3D) nodes holding an A-rich strip x in [lx/4, 3 lx/4)
+ * with the guessed bulk values guess = {nA_in, nB_in, nA_out, nB_out} (NULL:
+ * {1, 0.04, 0.04, 1}), in chunks of 2048 steps until no bulk concentration
+ * (strip centre x = lx/2, box edge x = 0) changes by more than tol over a
+ * chunk, or max_steps have run.  out[4] = {nA_in, nB_in, nA_out, nB_out};
+ * *steps (nullable) = steps run.  The workspace comes from
+ * scmc_flat_workspace_bytes; the call synchronises the stream.  Returns
+ * SCMC_ENONFINITE if the run diverges. */
+int scmc_flat_workspace_bytes(const scmc_problem *p, int lx, size_t *out);
+int scmc_flat_equilibrium(const scmc_problem *p, int lx, const double *guess,
+                          int64_t max_steps, double tol, void *d_ws,
+                          size_t ws_bytes, void *stream, double *out,
+                          int64_t *steps);
 
 /* Many independent lattices advanced by one persistent launch per step
  * (the paper's sweep over droplet sizes and couplings, Sec. 4).  Members may

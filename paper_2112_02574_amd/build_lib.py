@@ -13,17 +13,27 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libscmc.so")
-SOURCES = ["step_kernels.hip", "fused_kernels.hip", "obs_kernels.hip", "scmc_api.cpp"]
+# (source, object name, extra defines): the fused kernels are instantiated
+# once per storage format and stencil order so that they compile in parallel
+SOURCES = [("step_kernels.hip", "step_kernels", []),
+           ("fused_kernels.hip", "fused_kernels", []),
+           ("obs_kernels.hip", "obs_kernels", []),
+           ("scmc_api.cpp", "scmc_api", [])]
+for _st in ("StoreF32", "StoreF16", "StoreBF16"):
+    for _order in (4, 6):
+        SOURCES.append(("fused_inst.hip", f"fused_{_st}_{_order}",
+                        [f"-DSCMC_INST_STORE=scmc::{_st}", f"-DSCMC_INST_ORDER={_order}"]))
 ARCH = os.environ.get("SCMC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(item):
+    src, name, defines = item
+    obj = os.path.join(BUILD, name + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
-    cmd = ["hipcc"] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc"] + FLAGS + defines + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -33,7 +43,8 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    workers = min(len(SOURCES), os.cpu_count() or 1)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
         results = list(ex.map(_compile, SOURCES))
     for _, err in results:
         if verbose and err.strip():

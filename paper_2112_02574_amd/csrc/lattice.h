@@ -111,33 +111,48 @@ template <int D, int ORDER> struct Stencil {
 // ----------------------------------------------------------- storage formats
 // load(p, i, ref) returns the population in compute precision; ref = w_i n0_J
 // is the offset reference (used by the FP16 / BF16 offset formats only).
+// Stores are non-temporal: every population is written once per step and
+// only read again by the next step, after the whole buffer has streamed.
 struct StoreF64 {
     using T = double;
     using R = double;
     static constexpr int BYTES = 8;
+    __device__ __forceinline__ static R from_raw(T v, R) { return v; }
+    __device__ __forceinline__ static T to_raw(R v, R) { return v; }
     __device__ __forceinline__ static R load(const T *p, long i, R) { return p[i]; }
-    __device__ __forceinline__ static void store(T *p, long i, R v, R) { p[i] = v; }
-    __host__ __device__ static double decode(T v, double) { return v; }
+    __device__ __forceinline__ static void store(T *p, long i, R v, R) {
+        __builtin_nontemporal_store(v, p + i);
+    }
 };
 
 struct StoreF32 {
     using T = float;
     using R = float;
     static constexpr int BYTES = 4;
+    __device__ __forceinline__ static R from_raw(T v, R) { return v; }
+    __device__ __forceinline__ static T to_raw(R v, R) { return v; }
     __device__ __forceinline__ static R load(const T *p, long i, R) { return p[i]; }
-    __device__ __forceinline__ static void store(T *p, long i, R v, R) { p[i] = v; }
-    __host__ __device__ static double decode(T v, double) { return v; }
+    __device__ __forceinline__ static void store(T *p, long i, R v, R) {
+        __builtin_nontemporal_store(v, p + i);
+    }
 };
 
 struct StoreF16 {
     using T = uint16_t;
     using R = float;
     static constexpr int BYTES = 2;
+    __device__ __forceinline__ static R from_raw(T v, R ref) {
+        return __half2float(__ushort_as_half(v)) + ref;
+    }
+    __device__ __forceinline__ static T to_raw(R v, R ref) {
+        return __half_as_ushort(__float2half_rn(v - ref));
+    }
     __device__ __forceinline__ static R load(const T *p, long i, R ref) {
         return __half2float(__ushort_as_half(p[i])) + ref;
     }
     __device__ __forceinline__ static void store(T *p, long i, R v, R ref) {
-        p[i] = __half_as_ushort(__float2half_rn(v - ref));
+        const T h = __half_as_ushort(__float2half_rn(v - ref));
+        __builtin_nontemporal_store(h, p + i);
     }
 };
 
@@ -162,11 +177,18 @@ struct StoreBF16 {
     using T = uint16_t;
     using R = float;
     static constexpr int BYTES = 2;
+    __device__ __forceinline__ static R from_raw(T v, R ref) {
+        return bf16_to_f32(v) + ref;
+    }
+    __device__ __forceinline__ static T to_raw(R v, R ref) {
+        return f32_to_bf16_rne(v - ref);
+    }
     __device__ __forceinline__ static R load(const T *p, long i, R ref) {
         return bf16_to_f32(p[i]) + ref;
     }
     __device__ __forceinline__ static void store(T *p, long i, R v, R ref) {
-        p[i] = f32_to_bf16_rne(v - ref);
+        const T h = f32_to_bf16_rne(v - ref);
+        __builtin_nontemporal_store(h, p + i);
     }
 };
 

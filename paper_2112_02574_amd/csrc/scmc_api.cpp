@@ -178,6 +178,7 @@ struct scmc_batch {
     Member *d_members = nullptr;
     Tile *d_tiles = nullptr;
     int ntiles = 0;
+    int ntiles_cap = 0;  // tile-list capacity planned in the workspace
     int grid = 0;
     std::vector<bool> member_set;
 };
@@ -219,7 +220,7 @@ int validate(const scmc_problem *p, std::string *why) {
         return bad(SCMC_EINVAL, "unknown storage");
     if (p->psi_self != SCMC_PSI_N && p->psi_self != SCMC_PSI_EXP_NEG_INV)
         return bad(SCMC_EINVAL, "unknown psi");
-    if (p->kernel < SCMC_KERNEL_AUTO || p->kernel > SCMC_KERNEL_FUSED)
+    if (p->kernel < SCMC_KERNEL_AUTO || p->kernel > SCMC_KERNEL_FUSED_PIPE)
         return bad(SCMC_EINVAL, "unknown kernel design");
     const int r = stencil_radius(p->stencil);
     if (p->lattice == SCMC_D2Q9 && p->nz != 1)
@@ -254,6 +255,9 @@ StepKey key_of(const scmc_problem &p) {
     k.order = p.stencil;
     k.storage = p.storage;
     k.psi = p.psi_self;
+    k.repull = p.kernel == SCMC_KERNEL_FUSED_REPULL ? 1
+               : p.kernel == SCMC_KERNEL_FUSED_PIPE ? 2
+                                                    : 0;
     return k;
 }
 
@@ -294,7 +298,9 @@ int choose_kernel(const scmc_problem &p, const StepKey &k, int *kernel,
         for (int a = 0; a < 3; ++a) tile[a] = t[a];
         return SCMC_OK;
     }
-    if (p.kernel == SCMC_KERNEL_FUSED) return SCMC_EUNSUPPORTED;
+    if (p.kernel == SCMC_KERNEL_FUSED || p.kernel == SCMC_KERNEL_FUSED_REPULL ||
+        p.kernel == SCMC_KERNEL_FUSED_PIPE)
+        return SCMC_EUNSUPPORTED;
     *kernel = SCMC_KERNEL_TWO_PASS;
     tile[0] = tile[1] = tile[2] = 0;
     return SCMC_OK;
@@ -885,7 +891,11 @@ int scmc_observables(scmc_sim *s, int kind, double R0, scmc_obs *out,
 
 int scmc_config(scmc_sim *s, int *kernel, int *tile) {
     if (!s) return SCMC_EINVAL;
-    if (kernel) *kernel = s->c.kernel;
+    if (kernel)
+        *kernel = s->c.kernel != SCMC_KERNEL_FUSED ? s->c.kernel
+                  : s->c.key.repull == 1            ? SCMC_KERNEL_FUSED_REPULL
+                  : s->c.key.repull == 2            ? SCMC_KERNEL_FUSED_PIPE
+                                                    : SCMC_KERNEL_FUSED;
     if (tile)
         for (int a = 0; a < 3; ++a) tile[a] = s->c.tile[a];
     return SCMC_OK;
@@ -909,6 +919,72 @@ const char *scmc_status_str(int st) {
         case SCMC_ESTATE: return "bad call order";
     }
     return "unknown status";
+}
+
+// ------------------------------------------------------- flat steady state
+static scmc_problem flat_problem(const scmc_problem &p, int lx) {
+    scmc_problem q = p;
+    q.nx = lx;
+    q.ny = 5;
+    q.nz = p.lattice == SCMC_D2Q9 ? 1 : 5;
+    q.kernel = SCMC_KERNEL_TWO_PASS;  // a few thousand sites: launch-bound
+    return q;
+}
+
+int scmc_flat_workspace_bytes(const scmc_problem *p, int lx, size_t *out) {
+    if (!p || !out) return SCMC_EINVAL;
+    const scmc_problem q = flat_problem(*p, lx);
+    return scmc_workspace_bytes(&q, out);
+}
+
+int scmc_flat_equilibrium(const scmc_problem *p, int lx, const double *guess,
+                          int64_t max_steps, double tol, void *d_ws,
+                          size_t ws_bytes, void *stream, double *out,
+                          int64_t *steps) {
+    if (!p || !out || max_steps < 0 || !(tol >= 0)) return SCMC_EINVAL;
+    const double g0[4] = {1.0, 0.04, 0.04, 1.0};
+    const double *g = guess ? guess : g0;
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(g[k])) return SCMC_EINVAL;
+    const scmc_problem q = flat_problem(*p, lx);
+    scmc_sim *s = nullptr;
+    int rc = scmc_create(&q, d_ws, ws_bytes, stream, &s);
+    if (rc) return rc;
+    const size_t N = (size_t)q.nx * q.ny * q.nz;
+    std::vector<double> nA(N), nB(N);
+    for (size_t i = 0; i < N; ++i) {
+        const int x = (int)(i % q.nx);
+        const bool in = x >= lx / 4 && x < 3 * lx / 4;
+        nA[i] = in ? g[0] : g[2];
+        nB[i] = in ? g[1] : g[3];
+    }
+    rc = scmc_set_density(s, nA.data(), nB.data());
+    if (!rc) rc = scmc_set_graph_steps(s, 256);
+    // sample row y = z = 2 (any row: the state stays transverse-uniform)
+    const size_t row = ((size_t)(q.nz > 1 ? 2 : 0) * q.ny + 2) * q.nx;
+    double prev[4] = {0, 0, 0, 0};
+    int64_t done = 0;
+    bool converged = false;
+    while (!rc && !converged && done < max_steps) {
+        const int64_t k = std::min<int64_t>(2048, max_steps - done);
+        rc = scmc_step(s, k);
+        if (!rc) rc = scmc_get_fields(s, nA.data(), nB.data(), nullptr);
+        if (rc) break;
+        done += k;
+        const double cur[4] = {nA[row + lx / 2], nB[row + lx / 2], nA[row],
+                               nB[row]};
+        double d = 0;
+        for (int c = 0; c < 4; ++c) {
+            if (!std::isfinite(cur[c])) rc = SCMC_ENONFINITE;
+            d = std::max(d, std::fabs(cur[c] - prev[c]));
+            prev[c] = cur[c];
+        }
+        converged = done > k && d <= tol;
+    }
+    for (int c = 0; c < 4; ++c) out[c] = prev[c];
+    if (steps) *steps = done;
+    scmc_destroy(s);
+    return rc;
 }
 
 // ------------------------------------------------------------------ batch
@@ -991,6 +1067,7 @@ int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
                                     ? batch_tiles(v, c.kernel, tmin, &tiles)
                                     : 0);
     b->ntiles = batch_tiles(v, c.kernel, c.tile, &tiles);
+    b->ntiles_cap = std::max(nt_max, 1);
     const Plan pl = plan_of(v, std::max(nt_max, 1));
     c.stream = (hipStream_t)stream;
     c.ws = (char *)d_ws;
@@ -1126,18 +1203,206 @@ int scmc_batch_config(scmc_batch *b, int *tile, int *grid) {
     return SCMC_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+
+struct Candidate {
+    int variant;  // StepKey::repull
+    int tile[3];
+};
+
+// Fused candidates that this problem can run: register ring and pipelined
+// designs over the compiled tiles and three z-chunk lengths.
+std::vector<Candidate> candidates(const StepKey &k0, int nx) {
+    static const int tiles[][2] = {{64, 4}, {32, 8}, {64, 8}, {32, 16}, {128, 4}};
+    static const int chunks[] = {8, 16, 32};
+    std::vector<Candidate> out;
+    for (int variant : {0, 2})
+        for (const auto &t : tiles) {
+            if (t[0] > 2 * nx) continue;  // mostly idle lanes
+            for (int zc : chunks) {
+                Candidate c{variant, {t[0], t[1], zc}};
+                StepKey k = k0;
+                k.repull = variant;
+                if (fused_supported(k, c.tile)) out.push_back(c);
+            }
+        }
+    return out;
+}
+
+std::string cache_key(const scmc_problem &p, int count) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "lattice=%d stencil=%d storage=%d psi=%d box=%dx%dx%d members=%d",
+             p.lattice, p.stencil, p.storage, p.psi_self, p.nx, p.ny, p.nz, count);
+    return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, Candidate *c) {
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        const char *sep = strstr(line, " -> ");
+        if (!sep || std::string(line, sep - line) != key) continue;
+        Candidate t;
+        if (sscanf(sep + 4, "variant=%d tile=%d,%d,%d", &t.variant, &t.tile[0],
+                   &t.tile[1], &t.tile[2]) == 4) {
+            *c = t;  // the last entry for a key wins
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const Candidate &c,
+                 double us) {
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s -> variant=%d tile=%d,%d,%d  (%.2f us/step)\n", key.c_str(),
+            c.variant, c.tile[0], c.tile[1], c.tile[2], us);
+    fclose(f);
+}
+
+// Time `steps` launches of step() on the handle's stream, in microseconds.
+template <class StepFn>
+int time_steps(Common &c, int warm, int steps, StepFn step, double *us) {
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    int rc = SCMC_OK;
+    for (int i = 0; i < warm && !rc; ++i) rc = step();
+    if (!rc) {
+        (void)hipEventRecord(e0, c.stream);
+        for (int i = 0; i < steps && !rc; ++i) rc = step();
+        (void)hipEventRecord(e1, c.stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        *us = 1e3 * ms / steps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+void apply(Common &c, const Candidate &cand) {
+    c.kernel = SCMC_KERNEL_FUSED;
+    c.key.repull = cand.variant;
+    for (int a = 0; a < 3; ++a) c.tile[a] = cand.tile[a];
+    drop_graphs(c);
+}
+
+}  // namespace
+
+extern "C" {
+
 int scmc_autotune(scmc_sim *s, const char *cache_path, int *tile) {
-    (void)cache_path;
-    (void)tile;
     if (!s) return SCMC_EINVAL;
-    return fail(s->c, SCMC_EUNSUPPORTED, "autotuner needs the fused kernel");
+    Common &c = s->c;
+    const scmc_problem &p = s->lat.p;
+    if (p.kernel == SCMC_KERNEL_TWO_PASS)
+        return fail(c, SCMC_EUNSUPPORTED, "the two-pass design has no tile to tune");
+    std::vector<Candidate> cands = candidates(c.key, p.nx);
+    if (cands.empty())
+        return fail(c, SCMC_EUNSUPPORTED, "no fused kernel for this problem");
+    const std::string key = cache_key(p, 1);
+    Candidate best{};
+    if (!cache_lookup(cache_path, key, &best)) {
+        // scratch state: a uniform mixture at rest
+        std::vector<double> nA(s->lat.m.N, 0.5), nB(s->lat.m.N, 0.5);
+        int rc = set_density_impl(c, s->lat, nA.data(), nB.data(), c.pop[0]);
+        if (rc) return rc;
+        c.cur = 0;
+        double best_us = 1e300;
+        for (const Candidate &cand : cands) {
+            apply(c, cand);
+            double us = 0;
+            rc = time_steps(c, 2, 6, [&] { return direct_step_sim(s); }, &us);
+            if (rc) return rc;
+            if (us < best_us) {
+                best_us = us;
+                best = cand;
+            }
+        }
+        cache_store(cache_path, key, best, best_us);
+        c.initialized = false;  // the scratch state is not the caller's
+        c.step = 0;
+        c.cur = 0;
+    }
+    apply(c, best);
+    if (tile)
+        for (int a = 0; a < 3; ++a) tile[a] = best.tile[a];
+    return SCMC_OK;
 }
 
 int scmc_batch_autotune(scmc_batch *b, const char *cache_path, int *tile) {
-    (void)cache_path;
-    (void)tile;
     if (!b) return SCMC_EINVAL;
-    return fail(b->c, SCMC_EUNSUPPORTED, "autotuner needs the fused kernel");
+    Common &c = b->c;
+    const scmc_problem &p0 = b->lats[0].p;
+    if (p0.kernel == SCMC_KERNEL_TWO_PASS)
+        return fail(c, SCMC_EUNSUPPORTED, "the two-pass design has no tile to tune");
+    int nxmin = p0.nx;
+    std::vector<scmc_problem> ps;
+    for (const Lat &L : b->lats) {
+        nxmin = std::min(nxmin, L.p.nx);
+        ps.push_back(L.p);
+    }
+    std::vector<Candidate> cands = candidates(c.key, nxmin);
+    if (cands.empty())
+        return fail(c, SCMC_EUNSUPPORTED, "no fused kernel for this batch");
+    const std::string key = cache_key(p0, (int)b->lats.size());
+    auto use = [&](const Candidate &cand) -> int {
+        std::vector<Tile> tiles;
+        const int nt = batch_tiles(ps, SCMC_KERNEL_FUSED, cand.tile, &tiles);
+        if (nt > b->ntiles_cap)
+            return fail(c, SCMC_ENOSPACE, "tile list larger than planned");
+        apply(c, cand);
+        b->ntiles = nt;
+        HIPCHK(c, hipMemcpyAsync(b->d_tiles, tiles.data(), nt * sizeof(Tile),
+                                 hipMemcpyHostToDevice, c.stream));
+        HIPCHK(c, hipStreamSynchronize(c.stream));
+        return SCMC_OK;
+    };
+    Candidate best{};
+    if (!cache_lookup(cache_path, key, &best)) {
+        for (int i = 0; i < (int)b->lats.size(); ++i) {
+            std::vector<double> nA(b->lats[i].m.N, 0.5), nB(b->lats[i].m.N, 0.5);
+            int rc = set_density_impl(c, b->lats[i], nA.data(), nB.data(),
+                                      (void *)member_pop(b, i, 0));
+            if (rc) return rc;
+        }
+        c.cur = 0;
+        double best_us = 1e300;
+        for (const Candidate &cand : cands) {
+            if (cand.tile[0] > 2 * nxmin) continue;
+            int rc = use(cand);
+            if (rc == SCMC_ENOSPACE) continue;
+            if (rc) return rc;
+            double us = 0;
+            rc = time_steps(c, 1, 4, [&] { return direct_step_batch(b); }, &us);
+            if (rc) return rc;
+            if (us < best_us) {
+                best_us = us;
+                best = cand;
+            }
+        }
+        cache_store(cache_path, key, best, best_us);
+        c.initialized = false;
+        c.step = 0;
+        c.cur = 0;
+        std::fill(b->member_set.begin(), b->member_set.end(), false);
+    }
+    int rc = use(best);
+    if (rc) return rc;
+    if (tile)
+        for (int a = 0; a < 3; ++a) tile[a] = best.tile[a];
+    return SCMC_OK;
 }
 
 }  // extern "C"

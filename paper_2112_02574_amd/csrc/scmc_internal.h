@@ -35,6 +35,8 @@ struct StepKey {
     int order;    // 4, 6, 8
     int storage;  // StorageKind
     int psi;      // 0 / 1
+    int repull;   // fused design: 0 = register ring, 1 = re-pull at collide,
+                  // 2 = register ring with loads issued one plane ahead
 };
 
 // ---- step kernels (step_kernels.hip)

@@ -114,14 +114,14 @@ __device__ __forceinline__ void site_force(const Member &m,
     }
 }
 
-// Common velocity, BGK collision with Guo forcing, store of f*.
-template <int D, class ST>
-__device__ __forceinline__ void site_collide_store(
-    const Member &m, const typename ST::R (&f)[2][Lattice<D>::Q],
-    typename ST::R nA, typename ST::R nB, const typename ST::R (&FA)[3],
-    const typename ST::R (&FB)[3], typename ST::T *__restrict__ dst, long s) {
+// Common velocity, BGK collision with Guo forcing; every f*_i^J is handed to
+// sink(J, i, value, w_i n0_J) as soon as it is formed.
+template <int D, class R, class Sink>
+__device__ __forceinline__ void site_collide(const Member &m,
+                                             const R (&f)[2][Lattice<D>::Q],
+                                             R nA, R nB, const R (&FA)[3],
+                                             const R (&FB)[3], Sink &&sink) {
     using L = Lattice<D>;
-    using R = typename ST::R;
     R mx = 0, my = 0, mz = 0;
 #pragma unroll
     for (int J = 0; J < 2; ++J)
@@ -137,7 +137,6 @@ __device__ __forceinline__ void site_collide_store(
     const R uz = D == 3 ? (mz + R(0.5) * (FA[2] + FB[2])) * inv : R(0);
     const R uu = ux * ux + uy * uy + uz * uz;
     const R omega = (R)m.omega, cf = R(1) - R(0.5) * omega;
-    typename ST::T *base = dst + m.pop_off;
     const R n0[2] = {(R)m.n0[0], (R)m.n0[1]};
 #pragma unroll
     for (int J = 0; J < 2; ++J) {
@@ -154,8 +153,99 @@ __device__ __forceinline__ void site_collide_store(
                           (R(1) + R(3) * xu + R(4.5) * xu * xu - R(1.5) * uu);
             const R S = w * (R(3) * xF + R(9) * xu * xF - R(3) * uF);
             const R out = f[J][i] - omega * (f[J][i] - feq) + cf * S;
-            ST::store(base, (long)(J * L::Q + i) * m.N + s, out, w * n0[J]);
+            sink(J, i, out, w * n0[J]);
         }
+    }
+}
+
+// Collide and store f* at site s of the member's block of dst.
+template <int D, class ST>
+__device__ __forceinline__ void site_collide_store(
+    const Member &m, const typename ST::R (&f)[2][Lattice<D>::Q],
+    typename ST::R nA, typename ST::R nB, const typename ST::R (&FA)[3],
+    const typename ST::R (&FB)[3], typename ST::T *__restrict__ dst, long s) {
+    using R = typename ST::R;
+    typename ST::T *base = dst + m.pop_off;
+    site_collide<D, R>(m, f, nA, nB, FA, FB, [&](int J, int i, R v, R ref) {
+        ST::store(base, (long)(J * Lattice<D>::Q + i) * m.N + s, v, ref);
+    });
+}
+
+// ---- raw-buffer access with 32-bit offsets (used by the fused kernels) ----
+// One buffer descriptor per component covers its Q planes; lanes pass 32-bit
+// byte offsets, the plane offset goes in the scalar offset.  The hardware
+// returns 0 for reads and drops writes outside the descriptor's range.
+constexpr int BUF_DATA_FORMAT_32 = 0x00020000;
+constexpr int BUF_NT = 2;  // cache policy: non-temporal
+
+template <class T> struct RawBuf;
+template <> struct RawBuf<float> {
+    __device__ __forceinline__ static float load(__amdgpu_buffer_rsrc_t r, int v,
+                                                 int s) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+    }
+    __device__ __forceinline__ static void store_nt(float x, __amdgpu_buffer_rsrc_t r,
+                                                    int v, int s) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v,
+                                              s, BUF_NT);
+    }
+};
+template <> struct RawBuf<uint16_t> {
+    __device__ __forceinline__ static uint16_t load(__amdgpu_buffer_rsrc_t r, int v,
+                                                    int s) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0);
+    }
+    __device__ __forceinline__ static void store_nt(uint16_t x,
+                                                    __amdgpu_buffer_rsrc_t r, int v,
+                                                    int s) {
+        __builtin_amdgcn_raw_buffer_store_b16(x, r, v, s, BUF_NT);
+    }
+};
+
+template <class ST> struct PopBuf {
+    __amdgpu_buffer_rsrc_t r[2];
+    int plane_bytes;  // N * sizeof(T)
+};
+
+template <class ST, int Q>
+__device__ __forceinline__ PopBuf<ST> make_popbuf(const typename ST::T *pop,
+                                                  const Member &m) {
+    using T = typename ST::T;
+    PopBuf<ST> b;
+    const T *base = pop + m.pop_off;
+    const unsigned bytes = (unsigned)Q * (unsigned)m.N * (unsigned)sizeof(T);
+    b.r[0] = __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes,
+                                               BUF_DATA_FORMAT_32);
+    b.r[1] = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (long)Q * m.N), (short)0,
+                                               (int)bytes, BUF_DATA_FORMAT_32);
+    b.plane_bytes = m.N * (int)sizeof(T);
+    return b;
+}
+
+// Pull of site (x, y, z) through buffer descriptors (D3Q19).
+template <class ST>
+__device__ __forceinline__ void pull_site_buf(const Member &m, const PopBuf<ST> &b,
+                                              int x, int y, int z,
+                                              typename ST::R (&f)[2][19]) {
+    using L = Lattice<3>;
+    using T = typename ST::T;
+    using R = typename ST::R;
+    const int nxy = m.nx * m.ny;
+    int xo[3], yo[3], zo[3];  // index d + 1 holds coordinate + d, wrapped
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {
+        xo[d + 1] = wrap1(x + d, m.nx);
+        yo[d + 1] = wrap1(y + d, m.ny) * m.nx;
+        zo[d + 1] = wrap1(z + d, m.nz) * nxy;
+    }
+    const R n0A = (R)m.n0[0], n0B = (R)m.n0[1];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int s = zo[1 - L::CZ[i]] + yo[1 - L::CY[i]] + xo[1 - L::CX[i]];
+        const int voff = s * (int)sizeof(T), soff = i * b.plane_bytes;
+        const R w = (R)L::W[i];
+        f[0][i] = ST::from_raw(RawBuf<T>::load(b.r[0], voff, soff), w * n0A);
+        f[1][i] = ST::from_raw(RawBuf<T>::load(b.r[1], voff, soff), w * n0B);
     }
 }
 

@@ -81,13 +81,27 @@ def radius_field(nx, ny, nz=None):
     return np.sqrt((x - cx) ** 2.0 + (y - cy) ** 2.0 + (z - cz) ** 2.0)
 
 
-def droplet(nx, ny, nz=None, R=None, n_in=1.0, n_out=0.04, a_rich=True):
-    """tanh droplet of radius R (default L/4) centred on node floor(L/2)."""
+def droplet(nx, ny, nz=None, R=None, n_in=1.0, n_out=0.04, a_rich=True, bulk=None):
+    """tanh droplet of radius R (default L/4) centred on node floor(L/2).
+
+    Either the rich component goes from n_in (inside) to n_out (outside) and
+    the other the reverse, or ``bulk`` = (nA_in, nB_in, nA_out, nB_out) gives
+    all four bulk values (e.g. those of a converged flat interface, with
+    "in" the A-rich phase); ``a_rich`` then picks which phase is the droplet."""
     if R is None:
         R = nx / 4.0
     r = radius_field(nx, ny, nz)
-    rich = 0.5 * (n_in + n_out) - 0.5 * (n_in - n_out) * np.tanh(r - R)
-    poor = 0.5 * (n_out + n_in) - 0.5 * (n_out - n_in) * np.tanh(r - R)
+
+    def prof(inside, outside):
+        return 0.5 * (inside + outside) - 0.5 * (inside - outside) * np.tanh(r - R)
+
+    if bulk is not None:
+        a_in, b_in, a_out, b_out = bulk
+        if not a_rich:
+            a_in, b_in, a_out, b_out = a_out, b_out, a_in, b_in
+        return prof(a_in, a_out), prof(b_in, b_out)
+    rich = prof(n_in, n_out)
+    poor = prof(n_out, n_in)
     return (rich, poor) if a_rich else (poor, rich)
 
 

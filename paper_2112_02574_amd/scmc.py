@@ -20,7 +20,7 @@ D2Q9, D3Q19 = 0, 1
 E4, E6, E8 = 4, 6, 8
 PSI_N, PSI_EXP_NEG_INV = 0, 1
 F64, F32, F16_OFF, BF16_OFF = 0, 1, 2, 3
-KERNEL_AUTO, KERNEL_TWO_PASS, KERNEL_FUSED = 0, 1, 2
+KERNEL_AUTO, KERNEL_TWO_PASS, KERNEL_FUSED, KERNEL_FUSED_REPULL, KERNEL_FUSED_PIPE = 0, 1, 2, 3, 4
 OBS_FLAT, OBS_DROPLET = 0, 1
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16_OFF: "f16", BF16_OFF: "bf16"}
 
@@ -101,6 +101,11 @@ _SYMBOLS = {
     "scmc_autotune": ([ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "scmc_batch_autotune": ([ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "scmc_config": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "scmc_flat_workspace_bytes": ([ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+                                  ctypes.c_int),
+    "scmc_flat_equilibrium": ([ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                               ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "scmc_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
     "scmc_batch_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
     "scmc_status_str": ([ctypes.c_int], ctypes.c_char_p),
@@ -185,6 +190,29 @@ def _device_buffer(nbytes, device):
     if not torch.cuda.is_available():
         raise RuntimeError("libscmc needs a GPU (torch.cuda.is_available() is False)")
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def scmc_flat_equilibrium(p, lx=128, guess=None, max_steps=200000, tol=1e-12,
+                          device="cuda:0", stream=None):
+    """Bulk concentrations {nA_in, nB_in, nA_out, nB_out} of a converged flat
+    interface with the problem's couplings (the paper's first stage)."""
+    import torch
+    need = ctypes.c_size_t()
+    rc = lib().scmc_flat_workspace_bytes(ctypes.byref(p), int(lx), ctypes.byref(need))
+    if rc:
+        raise ScmcError(rc, "scmc_flat_workspace_bytes")
+    ws = _device_buffer(need.value, device)
+    with torch.cuda.device(ws.device):
+        st = stream if stream is not None else torch.cuda.current_stream()
+    g = None if guess is None else _f64(guess, 4)
+    out = np.zeros(4)
+    steps = ctypes.c_int64()
+    rc = lib().scmc_flat_equilibrium(ctypes.byref(p), int(lx), _ptr(g), int(max_steps), float(tol),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                     ctypes.c_void_p(st.cuda_stream), _ptr(out), ctypes.byref(steps))
+    if rc:
+        raise ScmcError(rc, "scmc_flat_equilibrium")
+    return out, steps.value
 
 
 class Sim:
