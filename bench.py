@@ -3,7 +3,9 @@
 Workload: D3Q19 droplet on a 128^3 periodic box, R0 = 24, tau = 1,
 g_AB = G c_s^2 = 1.8 (symmetric, psi = n), E6 force stencil, populations
 stored and updated in FP32 (structure-of-arrays), synthetic tanh initial
-profile of Sec. 4.  A timed step is one lattice update of both components
+profile of Sec. 4 between the bulk concentrations of a converged flat
+interface (the paper's two-stage initialisation, first stage run on the GPU
+before timing).  A timed step is one lattice update of both components
 (stream + concentrations + Shan-Chen force + common velocity + BGK/Guo
 collide); the FP64 statistics and the pressure-tensor / sigma[R] / R_s
 reductions run at the paper's monitoring cadence (every 2^11 steps, Sec. 4)
@@ -14,7 +16,10 @@ components), the roofline of the step kernel (algorithmic bytes 4 Q s per
 site = 304 B for FP32 over the event-timed kernel time, against the 8 TB/s
 HBM peak), the HBM traffic measured by rocprofv3 counters for the same
 kernel source when available, and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+sample of the same workload.  Beside it go the step rates of the other
+storage formats (FP64, FP16 and BF16 offsets) on the same droplet and of the
+48-member batched sweep (one persistent launch per step), each over a short
+timed run.
 """
 import argparse
 import hashlib
@@ -34,19 +39,23 @@ TRAFFIC_JSON = os.path.join(ROOT, "profiles", "fused_e6_f32_128cube_traffic.txt"
 TRACE_MD = os.path.join(ROOT, "profiles", "fused_e6_f32_128cube_kernel_trace.md")
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace "
-             "-o trace -- python3 bench.py --steps 300 --warmup 20 --cpu-steps 0",
+             "-o trace -- python3 bench.py --steps 300 --warmup 20 --cpu-steps 0 --variant-steps 0 --init tanh --kernel fused --tile 128 4 16",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch "
-             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0",
+             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh --kernel fused --tile 128 4 16",
     "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write "
-             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0",
+             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh --kernel fused --tile 128 4 16",
     "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_copy_fetch "
                   "-o cfetch -- python3 bench.py --copy-calib 1024",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_copy_write "
                   "-o cwrite -- python3 bench.py --copy-calib 1024",
 }
-KERNEL_SOURCES = ["paper_2112_02574_amd/csrc/fused_kernels.hip",
+KERNEL_SOURCES = ["paper_2112_02574_amd/csrc/fused_impl.h",
+                  "paper_2112_02574_amd/csrc/fused_inst.hip",
+                  "paper_2112_02574_amd/csrc/fused_kernels.hip",
                   "paper_2112_02574_amd/csrc/site_ops.h",
                   "paper_2112_02574_amd/csrc/lattice.h"]
+G_SYM = ((0.0, 1.8), (1.8, 0.0))
+G_ASYM = ((-0.2, 1.8), (1.8, 0.0))
 
 
 def kernel_source_hash():
@@ -137,7 +146,9 @@ def cpu_baseline(L, R0, steps):
     from oracle import oracle as O
     from paper_2112_02574_amd import inputs
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    o = O.Oracle(3, 6, (L, L, L), tau=1.0, g=((0.0, 1.8), (1.8, 0.0)), nthreads=threads)
+    o = O.Oracle(3, 6, (L, L, L), tau=1.0, g=G_SYM, nthreads=threads)
+    # the oracle takes no input from the GPU library, so it starts from the
+    # plain tanh droplet (1.0 / 0.04): the cost of a step does not depend on it
     o.set_density(*inputs.droplet(L, L, L, R=R0))
     o.run(1)  # first touch of the work arrays
     t0 = time.perf_counter()
@@ -145,8 +156,71 @@ def cpu_baseline(L, R0, steps):
     dt = time.perf_counter() - t0
     return {"value": round(L ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": f"FP64 oracle, {steps} steps of the same {L}^3 D3Q19/E6 droplet "
+            "sample": f"FP64 oracle, {steps} steps of a {L}^3 D3Q19/E6 droplet "
                       f"({L ** 3 * steps:.3g} site updates, {dt:.1f} s)"}
+
+
+def _timed(step, steps, stream):
+    """Event-timed milliseconds per step of ``step(n)`` on ``stream``."""
+    import torch
+    step(min(20, steps))
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    step(steps)
+    ev1.record(stream)
+    ev1.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def variants(args, L, R0, bulk, init, dev, stream):
+    """Step rates of the other storage formats on the same droplet, and of the
+    48-member batched sweep, each over ``args.variant_steps`` timed steps."""
+    from paper_2112_02574_amd import inputs
+    from paper_2112_02574_amd import scmc
+    N = L ** 3
+    n0 = (0.5 * (bulk[0] + bulk[2]), 0.5 * (bulk[1] + bulk[3]))
+    out = {}
+    for name, storage, size in (("f64", scmc.F64, 8), ("f16_offset", scmc.F16_OFF, 2),
+                                ("bf16_offset", scmc.BF16_OFF, 2)):
+        s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), g=G_SYM, storage=storage,
+                                  n0=n0), device=dev, stream=stream)
+        if storage != scmc.F64:
+            s.scmc_autotune(args.tune_cache)
+        s.scmc_set_density(*init)
+        ms = _timed(s.scmc_step, args.variant_steps, stream)
+        kernel, tile = s.scmc_config()
+        gbs = 4 * 19 * size * N / (ms * 1e-3) / 1e9
+        out[name] = {"MLUPS": round(N / (ms * 1e3), 1), "kernel": KERNEL_NAMES[kernel],
+                     "tile": list(tile), "bytes_per_site": 4 * 19 * size,
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        s.close()
+    # the batched sweep: 48 droplets on 48^3..160^3 boxes, symmetric and
+    # asymmetric couplings, FP32, one persistent launch per step
+    members = inputs.batch_members()
+    bulks = {0.0: bulk}
+    bulks[-0.2], _ = scmc.scmc_flat_equilibrium(
+        scmc.problem(scmc.D3Q19, scmc.E6, (128, 128, 128), g=G_ASYM, storage=scmc.F64),
+        lx=128, guess=inputs.FLAT_GUESS[-0.2], tol=1e-10, device=dev, stream=stream)
+    ps = [scmc.problem(scmc.D3Q19, scmc.E6, (m["L"],) * 3, g=m["g"], storage=scmc.F32)
+          for m in members]
+    b = scmc.Batch(ps, device=dev, stream=stream)
+    tile = b.scmc_batch_autotune(args.tune_cache)
+    for i, m in enumerate(members):
+        Lm = m["L"]
+        b.scmc_batch_set_density(i, *inputs.droplet(Lm, Lm, Lm, R=m["R0"], a_rich=m["a_rich"],
+                                                    bulk=bulks[m["g"][0][0]]))
+    b.scmc_batch_set_graph_steps(64)
+    ms = _timed(b.scmc_batch_step, args.variant_steps, stream)
+    sites = sum(m["L"] ** 3 for m in members)
+    gbs = 4 * 19 * 4 * sites / (ms * 1e-3) / 1e9
+    out["batch48_f32"] = {"MLUPS": round(sites / (ms * 1e3), 1), "sites": sites,
+                          "members": len(members), "tile": list(tile),
+                          "grid": b.scmc_batch_config()[1], "graph_steps": 64,
+                          "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    b.close()
+    out["steps_each"] = args.variant_steps
+    return out
 
 
 def run(args):
@@ -159,7 +233,15 @@ def run(args):
     N = L ** 3
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    p = scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), tau=1.0, g=((0.0, 1.8), (1.8, 0.0)),
+    if args.init == "flat":
+        # stage one of the initialisation: bulk values of a converged flat interface
+        bulk, flat_steps = scmc.scmc_flat_equilibrium(
+            scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), g=G_SYM, storage=scmc.F64),
+            lx=L, guess=inputs.FLAT_GUESS[0.0], tol=1e-10, device=dev, stream=stream)
+    else:
+        bulk, flat_steps = list(inputs.FLAT_GUESS[0.0]), 0
+    init = inputs.droplet(L, L, L, R=R0, bulk=bulk)
+    p = scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), tau=1.0, g=G_SYM,
                      storage=scmc.F32, kernel=KERNELS[args.kernel],
                      tile=tuple(args.tile) if args.tile else (0, 0, 0))
     sim = scmc.Sim(p, device=dev, stream=stream)
@@ -167,7 +249,7 @@ def run(args):
         sim.scmc_autotune(args.tune_cache)   # picks design and tile on this GPU
     if args.graph:
         sim.scmc_set_graph_steps(args.graph)
-    sim.scmc_set_density(*inputs.droplet(L, L, L, R=R0))
+    sim.scmc_set_density(*init)
     kernel, tile = sim.scmc_config()
 
     sim.scmc_step(args.warmup)
@@ -212,7 +294,7 @@ def run(args):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded tanh droplet, no dataset)",
+        "data": "synthetic (tanh droplet between flat-interface bulk values, no dataset)",
         "config": {"workload": f"D3Q19 E6 droplet {L}^3 R0={R0:g} tau=1 g_AB=1.8 psi=n FP32 SoA",
                    "sites": N, "kernel": KERNEL_NAMES[kernel],
                    "tile": list(tile), "graph_steps": args.graph,
@@ -223,9 +305,12 @@ def run(args):
                      "bytes_per_site": 4 * 19 * 4},
         "observables": {"dP": _finite(obs["dP"]), "R_s": _finite(obs["R_s"]),
                         "sigma_s": _finite(obs["sigma_s"]), "step": obs["step"],
-                        "mass": stats["mass"].tolist(), "max_u": _finite(stats["max_u"])},
+                        "mass": stats["mass"].tolist(), "max_u": _finite(stats["max_u"]),
+                        "init_bulk": [round(v, 12) for v in bulk], "flat_steps": flat_steps},
     }
     sim.close()
+    if args.variant_steps > 0:
+        line["variants"] = variants(args, L, R0, bulk, init, dev, stream)
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(L, R0, args.cpu_steps)
     print(json.dumps(line), flush=True)
@@ -234,7 +319,7 @@ def run(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=30000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--graph", type=int, default=0,
@@ -243,6 +328,13 @@ def main():
     ap.add_argument("--kernel", choices=sorted(KERNELS), default="auto")
     ap.add_argument("--tune-cache", default=os.path.join(os.environ.get("TMPDIR", "/tmp"),
                                                          "scmc_autotune.txt"))
+    ap.add_argument("--init", choices=("flat", "tanh"), default="flat",
+                    help="droplet bulk values: converged flat interface (default) or the "
+                         "plain 1.0 / 0.04 guess (no flat-interface run: used by the "
+                         "counter passes, whose per-dispatch counts do not depend on it)")
+    ap.add_argument("--variant-steps", type=int, default=300,
+                    help="timed steps of each storage variant and of the batched sweep "
+                         "(0 to skip)")
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps of the CPU baseline (0 to skip)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",

@@ -228,3 +228,40 @@ class Oracle:
         lib().orc_stats(ctypes.byref(self.p), _dp(self.f), _dp(out))
         return {"mass": out[0:2].copy(), "momentum": out[2:5].copy(),
                 "min_n": out[5:7].copy(), "max_u": out[7], "n_nonfinite": int(out[8])}
+
+
+def flat_equilibrium(dim, stencil, g, psi_self=PSI_N, tau=1.0, lx=128,
+                     guess=(1.0, 0.04, 0.04, 1.0), tol=1e-12, max_steps=200000,
+                     chunk=2048, nthreads=1):
+    """First stage of the two-stage initialisation of Sec. 4: relax a flat
+    interface to its steady state and return the bulk concentrations.
+
+    The box is lx x 5 (x 5 in 3D) periodic nodes; an A-rich strip
+    x in [lx/4, 3 lx/4) starts at guess = (nA_in, nB_in, nA_out, nB_out) and the
+    rest at the swapped phase.  The run goes in chunks of ``chunk`` steps until
+    no bulk value (strip centre x = lx/2, box edge x = 0, on one transverse row)
+    moves by more than ``tol`` over a chunk.  Returns ([nA_in, nB_in, nA_out,
+    nB_out], steps); raises FloatingPointError if the run diverges."""
+    shape = (5, lx) if dim == 2 else (5, 5, lx)
+    o = Oracle(dim, stencil, shape, tau=tau, g=g, psi_self=psi_self, nthreads=nthreads)
+    x = np.arange(lx)
+    inside = (x >= lx // 4) & (x < 3 * lx // 4)
+    nA = np.broadcast_to(np.where(inside, guess[0], guess[2]), o.shape).copy()
+    nB = np.broadcast_to(np.where(inside, guess[1], guess[3]), o.shape).copy()
+    o.set_density(nA, nB)
+    prev = np.zeros(4)
+    done = 0
+    while done < max_steps:
+        k = min(chunk, max_steps - done)
+        o.run(k)
+        done += k
+        n = o.density()
+        row = n[:, 2 if dim == 3 else 0, 2]
+        cur = np.array([row[0, lx // 2], row[1, lx // 2], row[0, 0], row[1, 0]])
+        if not np.all(np.isfinite(cur)):
+            raise FloatingPointError("flat interface run diverged")
+        change = np.max(np.abs(cur - prev))
+        prev = cur
+        if done > k and change <= tol:
+            break
+    return prev.tolist(), done

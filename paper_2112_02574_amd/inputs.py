@@ -127,14 +127,25 @@ def flat_strip(nx, ny, nz=None, x0=None, w=None, n_h=1.0, n_l=0.04, a_rich=True)
 
 def batch_members(count=48, seed=4):
     """The seeded droplet sweep: R0_i ~ U[8, 40]; L_i = clamp(8 ceil(4 R0_i / 8),
-    48, 160) (aspect ratio L/R = 4 as in Sec. 4); g_AA = 0 for even i and -0.2 for
-    odd i, g_BB = 0, g_AB = 1.8; A-rich droplet when floor(i/2) is even."""
+    48, 160) (aspect ratio L/R = 4 as in Sec. 4); g_AA = 0 for even i and -0.2
+    for odd i, g_BB = 0, g_AB = 1.8.  Symmetric members alternate A-rich and
+    B-rich droplets (A-rich when floor(i/2) is even); asymmetric members hold a
+    B-rich droplet, because the attractive A phase sits close to its spinodal
+    and an A-rich droplet of these sizes is driven over it by the Laplace
+    pressure."""
     rng = SplitMix64(seed)
     out = []
     for i in range(count):
         R0 = 8.0 + 32.0 * rng.uniform()
         L = min(max(8 * math.ceil(4.0 * R0 / 8.0), 48), 160)
+        sym = i % 2 == 0
         out.append({"index": i, "L": L, "R0": R0,
-                    "g": ((0.0 if i % 2 == 0 else -0.2, 1.8), (1.8, 0.0)),
-                    "a_rich": (i // 2) % 2 == 0})
+                    "g": ((0.0 if sym else -0.2, 1.8), (1.8, 0.0)),
+                    "a_rich": sym and (i // 2) % 2 == 0})
     return out
+
+
+# Starting guesses for the flat-interface stage, (nA_in, nB_in, nA_out, nB_out)
+# with "in" the A-rich phase: close to pressure balance, n/3 + g_AA n^2 / 2 equal
+# in both nearly pure phases.
+FLAT_GUESS = {0.0: (1.0, 0.04, 0.04, 1.0), -0.2: (1.0, 0.001, 0.001, 0.70)}

@@ -323,7 +323,8 @@ def test_autotune_picks_a_working_design(tmp_path):
     s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, shape, storage=scmc.F32))
     tile = s.scmc_autotune(cache)
     kernel, t2 = s.scmc_config()
-    assert t2 == tile and kernel in (scmc.KERNEL_FUSED, scmc.KERNEL_FUSED_PIPE)
+    assert t2 == tile and kernel in (scmc.KERNEL_FUSED, scmc.KERNEL_FUSED_REPULL,
+                                     scmc.KERNEL_FUSED_PIPE)
     assert open(cache).read().count("->") == 1
     with pytest.raises(scmc.ScmcError):   # the tuner's scratch state is not kept
         s.scmc_step(1)
@@ -356,3 +357,26 @@ def test_batch_autotune_and_graph():
         s.scmc_set_density(nA, nB)
         s.scmc_step(13)
         assert np.abs(b.scmc_batch_get_fields(i) - s.scmc_get_fields()).max() < 1e-5
+
+
+@pytest.mark.parametrize("lattice,stencil,gaa,lx", [
+    (scmc.D3Q19, scmc.E6, 0.0, 32), (scmc.D2Q9, scmc.E8, 0.0, 48),
+    (scmc.D2Q9, scmc.E4, -0.2, 64)])
+def test_flat_equilibrium_matches_oracle(lattice, stencil, gaa, lx):
+    """Stage one of the two-stage initialisation: the GPU flat-interface run
+    (FP64 storage) and the oracle's reach the same bulk concentrations after
+    the same number of steps."""
+    dim = 2 if lattice == scmc.D2Q9 else 3
+    g = ((gaa, 1.8), (1.8, 0.0))
+    guess = inputs.FLAT_GUESS[gaa]
+    want, wsteps = O.flat_equilibrium(dim, stencil, g, lx=lx, guess=guess, tol=1e-12)
+    p = scmc.problem(lattice, stencil, (lx, lx, lx)[:dim], g=g, storage=scmc.F64)
+    got, steps = scmc.scmc_flat_equilibrium(p, lx=lx, guess=guess, tol=1e-12)
+    # FP64 on both sides: the same stopping chunk and the same values, unless
+    # roundoff moves the stop by one chunk (then both sit within the slow
+    # mode's tail, well under 1e-10, of the common fixed point)
+    err = np.abs(np.array(got) - np.array(want)).max()
+    if steps == wsteps:
+        assert err < 1e-12, err
+    else:
+        assert abs(steps - wsteps) == 2048 and err < 1e-10, (steps, wsteps, err)

@@ -55,5 +55,7 @@ def test_batch_members_recipe():
         assert 8.0 <= d["R0"] < 40.0
         assert d["L"] % 8 == 0 and 48 <= d["L"] <= 160
         assert d["g"][0][0] == (0.0 if i % 2 == 0 else -0.2)
-        assert d["a_rich"] == ((i // 2) % 2 == 0)
+        assert d["a_rich"] == (i % 2 == 0 and (i // 2) % 2 == 0)
     assert m == inputs.batch_members()  # seeded
+    # both droplet kinds occur among the symmetric members
+    assert {d["a_rich"] for d in m[0::2]} == {True, False}

@@ -115,3 +115,44 @@ def test_critical_coupling_of_exp_pseudopotential():
     ns = np.linspace(0.2, 3.0, 200)
     Ps = np.array([o2.bulk_pressure(v, 0.0) for v in ns])
     assert np.all(np.diff(Ps) > 0)
+
+
+@pytest.mark.parametrize("dim,order,gaa,guess", [
+    (2, 4, 0.0, (1.0, 0.04, 0.04, 1.0)),
+    (2, 8, 0.0, (1.0, 0.04, 0.04, 1.0)),
+    (2, 4, -0.2, (1.0, 0.001, 0.001, 0.70)),
+])
+def test_flat_equilibrium_bulks_balance_pressure(dim, order, gaa, guess):
+    """Stage one of the Sec. 4 initialisation.  At a flat steady state the
+    pair forces cancel inside any slab of nodes, so the momentum balance
+    leaves equal bulk pressures (eq. of the bulk pressure) on both sides of
+    the interface, for every stencil; with symmetric couplings the two
+    phases are mirror images (n_A in one = n_B in the other).  The asymmetric
+    guess starts near pressure balance (n_A/3 - 0.1 n_A^2 = n_B/3): a guess far
+    from it drives the attractive A phase towards its spinodal, where the
+    strip splits and its centre is no longer a bulk phase (which this pin
+    then flags)."""
+    g = ((gaa, 1.8), (1.8, 0.0))
+    bulk, steps = O.flat_equilibrium(dim, order, g, lx=64, guess=guess, tol=1e-13)
+    assert steps < 200000
+    o = O.Oracle(dim, order, (5, 64), g=g)
+    p_in = o.bulk_pressure(bulk[0], bulk[1])
+    p_out = o.bulk_pressure(bulk[2], bulk[3])
+    assert abs(p_in - p_out) < 1e-8 * abs(p_in)
+    # a genuine two-phase state, not the mixed one
+    assert bulk[0] - bulk[2] > 0.5 and bulk[3] - bulk[1] > 0.5
+    if gaa == 0.0:
+        assert abs(bulk[0] - bulk[3]) < 1e-12 and abs(bulk[1] - bulk[2]) < 1e-12
+
+
+def test_flat_equilibrium_negative_control():
+    """An asymmetric state far from steady does not balance: guards the
+    pressure-balance pin against a trivially passing check (a symmetric
+    state balances by symmetry alone at any time)."""
+    g = ((-0.2, 1.8), (1.8, 0.0))
+    bulk, _ = O.flat_equilibrium(2, 4, g, lx=64, guess=(1.0, 0.001, 0.001, 0.70),
+                                 tol=0.0, max_steps=256, chunk=128)
+    o = O.Oracle(2, 4, (5, 64), g=g)
+    p_in = o.bulk_pressure(bulk[0], bulk[1])
+    p_out = o.bulk_pressure(bulk[2], bulk[3])
+    assert abs(p_in - p_out) > 1e-6
