@@ -32,8 +32,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = {"auto": 0, "two_pass": 1, "fused": 2, "fused_repull": 3, "fused_pipe": 4}
-KERNEL_NAMES = {0: "auto", 1: "two_pass", 2: "fused", 3: "fused_repull", 4: "fused_pipe"}
+KERNELS = {"auto": 0, "two_pass": 1, "fused": 2, "fused_repull": 3, "fused_pipe": 4,
+           "fused_mom": 5, "fused_mom_pipe": 6, "two_pass_mom": 7}
+KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 OBS_EVERY = 2048
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "fused_e6_f32_128cube_traffic.txt")
 TRACE_MD = os.path.join(ROOT, "profiles", "fused_e6_f32_128cube_kernel_trace.md")

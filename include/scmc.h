@@ -79,8 +79,21 @@ typedef enum {
     SCMC_KERNEL_FUSED_REPULL = 3, /* same, but the populations of the
                                      collided plane are pulled again (from
                                      cache) instead of held in registers */
-    SCMC_KERNEL_FUSED_PIPE = 4    /* fused, with the next plane's loads issued
+    SCMC_KERNEL_FUSED_PIPE = 4,   /* fused, with the next plane's loads issued
                                      before the current plane's collision */
+    SCMC_KERNEL_FUSED_MOM = 5,    /* fused for tau = 1 only: the collision
+                                     then depends on the pulled populations
+                                     only through n_J and the total momentum,
+                                     so five moments per node wait in
+                                     registers instead of 2Q populations;
+                                     the default when tau = 1 */
+    SCMC_KERNEL_FUSED_MOM_PIPE = 6, /* the same with the next plane's loads
+                                       issued early (tau = 1 only) */
+    SCMC_KERNEL_TWO_PASS_MOM = 7  /* two passes for tau = 1 only: the first
+                                     pulls and stores n_J and the momentum,
+                                     the second collides from those moments
+                                     without pulling again (every lattice,
+                                     stencil and storage) */
 } scmc_kernel;
 typedef enum { SCMC_OBS_FLAT = 0, SCMC_OBS_DROPLET = 1 } scmc_obs_kind;
 

@@ -44,68 +44,91 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
     return start + k;
 }
 
-// Force from the LDS concentration ring, then velocity, collision and store
-// of one node of plane zc (collided at march step k).
+// Concentrations of node (tx, ty) of the plane collided at march step k and
+// the Shan-Chen forces on both components, from the LDS concentration ring
+// (planes k - 2 ZR .. k of the ring hold z - ZR .. z + ZR).
+template <int TX, int TY, int ORDER, class R, int PSI>
+__device__ __forceinline__ void lds_force(
+    const Member &m,
+    float2 (*lds)[TY + 2 * FusedGeom<ORDER>::HR][TX + 2 * FusedGeom<ORDER>::HR],
+    int k, int tx, int ty, R &nA, R &nB, R (&FA)[3], R (&FB)[3]) {
+    using G = FusedGeom<ORDER>;
+    using Sten = Stencil<3, ORDER>;
+    constexpr int HR = G::HR, ZR = G::ZR;
+    const float2 own = lds[(k - ZR) % G::NSLOT][ty + HR][tx + HR];
+    nA = own.x;
+    nB = own.y;
+    R cA[3] = {0, 0, 0}, cB[3] = {0, 0, 0}, sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0};
+    const bool selfA = m.self_on & 1, selfB = m.self_on & 2;
+#pragma unroll
+    for (int a = 0; a < Sten::NE; ++a) {
+        constexpr auto T = Sten::T;
+        const int ex = T.e[a][0], ey = T.e[a][1], ez = T.e[a][2];
+        const float2 d = lds[(k - ZR + ez) % G::NSLOT][ty + HR + ey][tx + HR + ex];
+        const R nAt = d.x, nBt = d.y;
+        const R W = (R)T.W[a];
+        const int e3[3] = {ex, ey, ez};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (e3[c] == 0) continue;
+            const R We = W * (R)e3[c];
+            cA[c] += We * nBt;
+            cB[c] += We * nAt;
+        }
+        if (selfA || selfB) {
+            const R pA = psi_of<R, PSI>(nAt), pB = psi_of<R, PSI>(nBt);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (e3[c] == 0) continue;
+                const R We = W * (R)e3[c];
+                sA[c] += We * pA;
+                sB[c] += We * pB;
+            }
+        }
+    }
+    const R gAB = (R)m.g[0][1], gBA = (R)m.g[1][0];
+    const R gAA = (R)m.g[0][0], gBB = (R)m.g[1][1];
+    const R pA = selfA ? psi_of<R, PSI>(nA) : R(0);
+    const R pB = selfB ? psi_of<R, PSI>(nB) : R(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        FA[c] = -gAB * nA * cA[c] - gAA * pA * sA[c];
+        FB[c] = -gBA * nB * cB[c] - gBB * pB * sB[c];
+    }
+}
+
+// Force, velocity, collision and store of node (tx, ty) of plane zc, collided
+// at march step k, from its pulled populations f.
 template <int TX, int TY, int ORDER, class ST, int PSI>
 __device__ __forceinline__ void fused_collide(
     const Member &m, const PopBuf<ST> &dst,
     float2 (*lds)[TY + 2 * FusedGeom<ORDER>::HR][TX + 2 * FusedGeom<ORDER>::HR],
     const typename ST::R (&f)[2][19], int k, int x0, int y0, int zc, int tx,
     int ty) {
-    using G = FusedGeom<ORDER>;
     using R = typename ST::R;
-    constexpr int HR = G::HR, ZR = G::ZR;
-    {
-        using Sten = Stencil<3, ORDER>;
-        const float2 own = lds[(k - ZR) % G::NSLOT][ty + HR][tx + HR];
-        const R nA = own.x, nB = own.y;
-        R cA[3] = {0, 0, 0}, cB[3] = {0, 0, 0}, sA[3] = {0, 0, 0},
-          sB[3] = {0, 0, 0};
-        const bool selfA = m.self_on & 1, selfB = m.self_on & 2;
-#pragma unroll
-        for (int a = 0; a < Sten::NE; ++a) {
-            constexpr auto T = Sten::T;
-            const int ex = T.e[a][0], ey = T.e[a][1], ez = T.e[a][2];
-            const float2 d = lds[(k - ZR + ez) % G::NSLOT][ty + HR + ey][tx + HR + ex];
-            const R nAt = d.x, nBt = d.y;
-            const R W = (R)T.W[a];
-            const int e3[3] = {ex, ey, ez};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (e3[c] == 0) continue;
-                const R We = W * (R)e3[c];
-                cA[c] += We * nBt;
-                cB[c] += We * nAt;
-            }
-            if (selfA || selfB) {
-                const R pA = psi_of<R, PSI>(nAt), pB = psi_of<R, PSI>(nBt);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    if (e3[c] == 0) continue;
-                    const R We = W * (R)e3[c];
-                    sA[c] += We * pA;
-                    sB[c] += We * pB;
-                }
-            }
-        }
-        const R gAB = (R)m.g[0][1], gBA = (R)m.g[1][0];
-        const R gAA = (R)m.g[0][0], gBB = (R)m.g[1][1];
-        const R pA = selfA ? psi_of<R, PSI>(nA) : R(0);
-        const R pB = selfB ? psi_of<R, PSI>(nB) : R(0);
-        R FA[3], FB[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            FA[c] = -gAB * nA * cA[c] - gAA * pA * sA[c];
-            FB[c] = -gBA * nB * cB[c] - gBB * pB * sB[c];
-        }
-        using T = typename ST::T;
-        const int voff =
-            (((zc * m.ny) + (y0 + ty)) * m.nx + (x0 + tx)) * (int)sizeof(T);
-        site_collide<3, R>(m, f, nA, nB, FA, FB, [&](int J, int i, R v, R ref) {
-            RawBuf<T>::store_nt(ST::to_raw(v, ref), dst.r[J], voff,
-                                i * dst.plane_bytes);
-        });
-    }
+    using T = typename ST::T;
+    R nA, nB, FA[3], FB[3];
+    lds_force<TX, TY, ORDER, R, PSI>(m, lds, k, tx, ty, nA, nB, FA, FB);
+    const int voff = (((zc * m.ny) + (y0 + ty)) * m.nx + (x0 + tx)) * (int)sizeof(T);
+    site_collide<3, R>(m, f, nA, nB, FA, FB, [&](int J, int i, R v, R ref) {
+        RawBuf<T>::store_nt(ST::to_raw(v, ref), dst.r[J], voff, i * dst.plane_bytes);
+    });
+}
+
+// The same at omega = 1 from the node's moments (n_A, n_B, j).
+template <int TX, int TY, int ORDER, class ST, int PSI>
+__device__ __forceinline__ void fused_collide_mom(
+    const Member &m, const PopBuf<ST> &dst,
+    float2 (*lds)[TY + 2 * FusedGeom<ORDER>::HR][TX + 2 * FusedGeom<ORDER>::HR],
+    const typename ST::R (&mom)[5], int k, int x0, int y0, int zc, int tx, int ty) {
+    using R = typename ST::R;
+    using T = typename ST::T;
+    R nA, nB, FA[3], FB[3];
+    lds_force<TX, TY, ORDER, R, PSI>(m, lds, k, tx, ty, nA, nB, FA, FB);
+    const int voff = (((zc * m.ny) + (y0 + ty)) * m.nx + (x0 + tx)) * (int)sizeof(T);
+    collide_tau1<3, R>(m, mom, FA, FB, [&](int J, int i, R v, R ref) {
+        RawBuf<T>::store_nt(ST::to_raw(v, ref), dst.r[J], voff, i * dst.plane_bytes);
+    });
 }
 
 template <int TX, int TY, int ORDER, class ST, int PSI, int REPULL, int S>
@@ -213,6 +236,39 @@ __device__ __forceinline__ void halo_pos(int h, int wx, int wy, int &lx, int &ly
         const int r = q / bw;
         ly = HR + wy + r;
         lx = q - r * bw;
+    }
+}
+
+// Tiles that span the whole x extent (wx == nx, one tile per row) take their
+// x halo from their own rows: the periodic images of the first and last HR
+// columns are written to LDS beside the row, and only the HR rows above and
+// below are pulled (2 HR wx nodes, coalesced, instead of the general halo).
+template <int HR>
+__device__ __forceinline__ int halo_count(int wx, int wy, bool full_row) {
+    return full_row ? 2 * HR * wx : 2 * HR * (wx + 2 * HR) + wy * 2 * HR;
+}
+
+template <int HR>
+__device__ __forceinline__ void halo_node(int h, int wx, int wy, bool full_row,
+                                          int &lx, int &ly) {
+    if (full_row) {
+        const int r = h / wx;
+        lx = HR + (h - r * wx);
+        ly = r < HR ? r : wy + r;
+    } else {
+        halo_pos<HR>(h, wx, wy, lx, ly);
+    }
+}
+
+// Store a concentration pair at LDS column lx of a row, plus its periodic
+// image when the tile spans the row.
+template <int HR, int W>
+__device__ __forceinline__ void put_lds(float2 (&row)[W], int lx, float2 v, int wx,
+                                        bool full_row) {
+    row[lx] = v;
+    if (full_row) {
+        if (lx < 2 * HR) row[lx + wx] = v;
+        else if (lx >= wx) row[lx - wx] = v;
     }
 }
 
@@ -345,8 +401,183 @@ __device__ __forceinline__ void fused_tile(const Member &m,
     }
 }
 
+// ---- omega = 1: moment ring
+// At tau = 1 the collision forgets the pre-collision populations except for
+// n_J and the total momentum j, so the march keeps those five moments per node
+// and plane instead of the 2Q populations.  The register ring shrinks from
+// (ZR + 1) x 2Q to (ZR + 1) x 5 values, which lets more waves share a SIMD
+// (and larger tiles fit), while the HBM traffic stays 2Q reads + 2Q writes.
+template <int TX, int TY, int ORDER, class ST, int PSI>
+__device__ __forceinline__ void fused_tile_mom(const Member &m,
+                                               const typename ST::T *__restrict__ src,
+                                               typename ST::T *__restrict__ dst,
+                                               int x0, int y0, int z0, int len) {
+    using G = FusedGeom<ORDER>;
+    using R = typename ST::R;
+    constexpr int HR = G::HR, ZR = G::ZR, NSLOT = G::NSLOT, NR = ZR + 1;
+    constexpr int NT = TX * TY;
+    __shared__ float2 lds[NSLOT][TY + 2 * HR][TX + 2 * HR];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const int wx = min(TX, m.nx - x0), wy = min(TY, m.ny - y0);
+    const bool active = tx < wx && ty < wy;
+    const bool full_row = wx == m.nx;
+    const int nhalo = halo_count<HR>(wx, wy, full_row);
+    const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
+    const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
+    R mom[NR][5];
+    const int kend = len + 2 * ZR;
+    for (int k0 = 0; k0 < kend; k0 += NR) {
+        static_for<0, NR>([&](auto sc) {
+            constexpr int S = decltype(sc)::value;
+            const int k = k0 + S;
+            if (k >= kend) return;
+            // lead plane z0 - ZR + k: moments of the tile, concentrations of
+            // tile and halo into LDS
+            const int zl = wrap1(z0 - ZR + k, m.nz);
+            auto &plane = lds[k % NSLOT];
+            if (active) {
+                R f[2][19];
+                pull_site_buf<ST>(m, sb, x0 + tx, y0 + ty, zl, f);
+                site_moments<3, R>(f, mom[S]);
+                put_lds<HR>(plane[ty + HR], tx + HR,
+                            make_float2((float)mom[S][0], (float)mom[S][1]), wx, full_row);
+            }
+            for (int h = tid; h < nhalo; h += NT) {
+                int lx, ly;
+                halo_node<HR>(h, wx, wy, full_row, lx, ly);
+                R f[2][19], nA, nB;
+                pull_site_buf<ST>(m, sb, wrap1(x0 - HR + lx, m.nx),
+                                  wrap1(y0 - HR + ly, m.ny), zl, f);
+                site_density<3, R>(f, nA, nB);
+                put_lds<HR>(plane[ly], lx, make_float2((float)nA, (float)nB), wx, full_row);
+            }
+            __syncthreads();
+            // collide plane z0 + k - 2 ZR, the lead plane of step k - ZR
+            if (k >= 2 * ZR && active)
+                fused_collide_mom<TX, TY, ORDER, ST, PSI>(
+                    m, db, lds, mom[(S + 1) % NR], k, x0, y0,
+                    wrap1(z0 + k - 2 * ZR, m.nz), tx, ty);
+        });
+    }
+}
+
+// The moment ring with the next lead plane's loads (tile and halo) issued
+// right after the barrier, before the current collision, as in
+// fused_tile_pipe; the loaded populations wait in registers (2 x 2Q values)
+// until the top of the next step.
+template <int TX, int TY, int ORDER, class ST, int PSI>
+__device__ __forceinline__ void fused_tile_mom_pipe(const Member &m,
+                                                    const typename ST::T *__restrict__ src,
+                                                    typename ST::T *__restrict__ dst,
+                                                    int x0, int y0, int z0, int len) {
+    using G = FusedGeom<ORDER>;
+    using R = typename ST::R;
+    constexpr int HR = G::HR, ZR = G::ZR, NSLOT = G::NSLOT, NR = ZR + 1;
+    __shared__ float2 lds[NSLOT][TY + 2 * HR][TX + 2 * HR];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const int wx = min(TX, m.nx - x0), wy = min(TY, m.ny - y0);
+    const bool active = tx < wx && ty < wy;
+    const bool full_row = wx == m.nx;
+    const int nhalo = halo_count<HR>(wx, wy, full_row);
+    const bool has_halo = tid < nhalo;
+    int hlx = 0, hly = 0;
+    if (has_halo) halo_node<HR>(tid, wx, wy, full_row, hlx, hly);
+    const int hgx = wrap1(x0 - HR + hlx, m.nx), hgy = wrap1(y0 - HR + hly, m.ny);
+    const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
+    const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
+    R mom[NR][5];  // plane z0 + p lives in mom[p % NR]
+    R fo[2][19], H[2][19];
+
+    auto put_density = [&](float2(&plane)[TY + 2 * HR][TX + 2 * HR], int ly, int lx,
+                           const R(&f)[2][19]) {
+        R nA, nB;
+        site_density<3, R>(f, nA, nB);
+        put_lds<HR>(plane[ly], lx, make_float2((float)nA, (float)nB), wx, full_row);
+    };
+
+    // prologue: planes z0 - ZR .. z0 + ZR - 1 into LDS slots 0 .. 2 ZR - 1
+    static_for<-ZR, ZR>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        const int z = wrap1(z0 + r, m.nz);
+        auto &plane = lds[(r + ZR) % NSLOT];
+        if (active) {
+            pull_site_buf<ST>(m, sb, x0 + tx, y0 + ty, z, fo);
+            if constexpr (r >= 0) {
+                site_moments<3, R>(fo, mom[r % NR]);
+                put_lds<HR>(plane[ty + HR], tx + HR,
+                            make_float2((float)mom[r % NR][0], (float)mom[r % NR][1]),
+                            wx, full_row);
+            } else {
+                put_density(plane, ty + HR, tx + HR, fo);
+            }
+        }
+        if (has_halo) {
+            pull_site_buf<ST>(m, sb, hgx, hgy, z, H);
+            put_density(plane, hly, hlx, H);
+        }
+    });
+    {   // first lead plane z0 + ZR
+        const int z = wrap1(z0 + ZR, m.nz);
+        if (active) pull_site_buf<ST>(m, sb, x0 + tx, y0 + ty, z, fo);
+        if (has_halo) pull_site_buf<ST>(m, sb, hgx, hgy, z, H);
+    }
+    for (int j0 = 0; j0 < len; j0 += NR) {
+        static_for<0, NR>([&](auto sc) {
+            constexpr int S = decltype(sc)::value;
+            const int j = j0 + S;
+            if (j >= len) return;
+            // consume the lead plane z0 + j + ZR
+            auto &plane = lds[(j + 2 * ZR) % NSLOT];
+            if (active) {
+                site_moments<3, R>(fo, mom[(S + ZR) % NR]);
+                put_lds<HR>(plane[ty + HR], tx + HR,
+                            make_float2((float)mom[(S + ZR) % NR][0],
+                                        (float)mom[(S + ZR) % NR][1]),
+                            wx, full_row);
+            }
+            if (has_halo) put_density(plane, hly, hlx, H);
+            __syncthreads();
+            // issue the next lead plane
+            if (j + 1 < len) {
+                const int z = wrap1(z0 + j + ZR + 1, m.nz);
+                if (active) pull_site_buf<ST>(m, sb, x0 + tx, y0 + ty, z, fo);
+                if (has_halo) pull_site_buf<ST>(m, sb, hgx, hgy, z, H);
+            }
+            // collide plane z0 + j
+            if (active)
+                fused_collide_mom<TX, TY, ORDER, ST, PSI>(m, db, lds, mom[S % NR],
+                                                          j + 2 * ZR, x0, y0,
+                                                          wrap1(z0 + j, m.nz), tx, ty);
+        });
+    }
+}
+
+// March the column tile (x0, y0), z-chunk [z0, z0 + len) with design VAR.
+template <int TX, int TY, int ORDER, class ST, int PSI, int VAR>
+__device__ __forceinline__ void fused_tile_any(const Member &m,
+                                               const typename ST::T *__restrict__ src,
+                                               typename ST::T *__restrict__ dst,
+                                               int x0, int y0, int z0, int len) {
+    if constexpr (VAR == 2)
+        fused_tile_pipe<TX, TY, ORDER, ST, PSI>(m, src, dst, x0, y0, z0, len);
+    else if constexpr (VAR == 3)
+        fused_tile_mom<TX, TY, ORDER, ST, PSI>(m, src, dst, x0, y0, z0, len);
+    else if constexpr (VAR == 4)
+        fused_tile_mom_pipe<TX, TY, ORDER, ST, PSI>(m, src, dst, x0, y0, z0, len);
+    else
+        fused_tile<TX, TY, ORDER, ST, PSI, VAR>(m, src, dst, x0, y0, z0, len);
+}
+
+// Waves per SIMD the compiler is asked to allow for: the population-ring
+// designs need most of the register file, the moment ring fits four waves,
+// its pipelined form (two planes of loads in flight) two.
+template <int VAR> constexpr int fused_waves() {
+    return VAR == 3 ? 4 : VAR == 4 ? 2 : 1;
+}
+
 template <int TX, int TY, int ORDER, class ST, int PSI, int VAR>
 __global__ void __launch_bounds__(TX *TY)
+    __attribute__((amdgpu_waves_per_eu(fused_waves<VAR>())))
     k_fused(Member m, const typename ST::T *__restrict__ src,
             typename ST::T *__restrict__ dst, int zc_len) {
     const int ntx = (m.nx + TX - 1) / TX, nty = (m.ny + TY - 1) / TY;
@@ -355,16 +586,12 @@ __global__ void __launch_bounds__(TX *TY)
     const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
     const int z0 = bz * zc_len;
     const int len = min(zc_len, m.nz - z0);
-    if constexpr (VAR == 2)
-        fused_tile_pipe<TX, TY, ORDER, ST, PSI>(m, src, dst, bx * TX, by * TY, z0,
-                                                len);
-    else
-        fused_tile<TX, TY, ORDER, ST, PSI, VAR>(m, src, dst, bx * TX, by * TY, z0,
-                                                len);
+    fused_tile_any<TX, TY, ORDER, ST, PSI, VAR>(m, src, dst, bx * TX, by * TY, z0, len);
 }
 
 template <int TX, int TY, int ORDER, class ST, int PSI, int VAR>
 __global__ void __launch_bounds__(TX *TY)
+    __attribute__((amdgpu_waves_per_eu(fused_waves<VAR>())))
     kb_fused(const Member *__restrict__ members, const Tile *__restrict__ tiles,
              int ntiles, const typename ST::T *__restrict__ src,
              typename ST::T *__restrict__ dst, int zc_len) {
@@ -372,19 +599,25 @@ __global__ void __launch_bounds__(TX *TY)
         const Tile tl = tiles[t];
         const Member m = members[tl.member];
         const int len = min(zc_len, m.nz - tl.z0);
-        if constexpr (VAR == 2)
-            fused_tile_pipe<TX, TY, ORDER, ST, PSI>(m, src, dst, tl.x0, tl.y0,
-                                                    tl.z0, len);
-        else
-            fused_tile<TX, TY, ORDER, ST, PSI, VAR>(m, src, dst, tl.x0, tl.y0,
-                                                    tl.z0, len);
+        fused_tile_any<TX, TY, ORDER, ST, PSI, VAR>(m, src, dst, tl.x0, tl.y0, tl.z0,
+                                                    len);
         __syncthreads();  // the next tile reuses the LDS ring
     }
 }
 
 // ---------------------------------------------------------------- dispatch
 // compiled tiles (TX, TY); the z-chunk is a runtime argument
-#define SCMC_FUSED_TILES(X) X(64, 4) X(32, 8) X(64, 8) X(32, 16) X(128, 4)
+#define SCMC_FUSED_TILES(X) \
+    X(64, 4) X(32, 8) X(64, 8) X(32, 16) X(128, 4) X(128, 8) X(64, 16)
+
+// Designs a tile is compiled for: 1024-thread tiles only with the plain
+// moment ring (the others do not fit four waves per SIMD); the pipelined
+// designs only where every thread owns at most one halo node.
+template <int VAR, int TX, int TY, int ORDER> constexpr bool fused_valid() {
+    if (TX * TY > 512 && VAR != 3) return false;
+    if ((VAR == 2 || VAR == 4) && !pipe_fits<TX, TY, ORDER>()) return false;
+    return true;
+}
 
 inline int fused_blocks(const Member &m, const int *tile) {
     const int ntx = (m.nx + tile[0] - 1) / tile[0];
@@ -403,7 +636,7 @@ template <class ST, int ORDER> struct FusedOps {
             auto with_r = [&](auto Rc) {
 #define SCMC_TRY(TXv, TYv)                                                   \
     if (tile[0] == TXv && tile[1] == TYv) {                                  \
-        if constexpr (decltype(Rc)::value != 2 || pipe_fits<TXv, TYv, ORDER>()) { \
+        if constexpr (fused_valid<decltype(Rc)::value, TXv, TYv, ORDER>()) { \
             fn(Pc, Rc, std::integral_constant<int, TXv>{},                   \
                std::integral_constant<int, TYv>{});                          \
             ok = true;                                                       \
@@ -413,9 +646,13 @@ template <class ST, int ORDER> struct FusedOps {
                 SCMC_FUSED_TILES(SCMC_TRY)
 #undef SCMC_TRY
             };
-            if (k.repull == 1) with_r(std::integral_constant<int, 1>{});
-            else if (k.repull == 2) with_r(std::integral_constant<int, 2>{});
-            else with_r(std::integral_constant<int, 0>{});
+            switch (k.repull) {
+                case 1: with_r(std::integral_constant<int, 1>{}); break;
+                case 2: with_r(std::integral_constant<int, 2>{}); break;
+                case 3: with_r(std::integral_constant<int, 3>{}); break;
+                case 4: with_r(std::integral_constant<int, 4>{}); break;
+                default: with_r(std::integral_constant<int, 0>{}); break;
+            }
         };
         if (k.psi == 0) with_p(std::integral_constant<int, 0>{});
         else with_p(std::integral_constant<int, 1>{});

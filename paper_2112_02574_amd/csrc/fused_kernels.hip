@@ -13,7 +13,7 @@ SCMC_FUSED_COMBOS(SCMC_EXTERN)
 #undef SCMC_EXTERN
 
 template <class F> static bool with_ops(const StepKey &k, F &&fn) {
-    if (k.dim != 3 || (k.order != 4 && k.order != 6)) return false;
+    if (k.dim != 3 || (k.order != 4 && k.order != 6) || k.big) return false;
     auto go = [&](auto stv) {
         using ST = decltype(stv);
         if (k.order == 4) return fn(FusedOps<ST, 4>{});

@@ -47,6 +47,21 @@ template <> struct Lattice<3> {
         1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 };
 
+// opp[i] = index of the velocity opposite to xi_i
+template <int D> struct Opposite {
+    int opp[Lattice<D>::Q];
+    static constexpr Opposite make() {
+        using L = Lattice<D>;
+        Opposite o{};
+        for (int i = 0; i < L::Q; ++i)
+            for (int j = 0; j < L::Q; ++j)
+                if (L::CX[j] == -L::CX[i] && L::CY[j] == -L::CY[i] &&
+                    L::CZ[j] == -L::CZ[i])
+                    o.opp[i] = j;
+        return o;
+    }
+};
+
 // ------------------------------------------------------------ force stencils
 constexpr double stencil_weight(int D, int order, int s) {
     if (D == 2 && order == 4) return s == 1 ? 1.0 / 3 : s == 2 ? 1.0 / 12 : 0.0;

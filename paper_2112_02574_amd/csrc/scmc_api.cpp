@@ -220,7 +220,7 @@ int validate(const scmc_problem *p, std::string *why) {
         return bad(SCMC_EINVAL, "unknown storage");
     if (p->psi_self != SCMC_PSI_N && p->psi_self != SCMC_PSI_EXP_NEG_INV)
         return bad(SCMC_EINVAL, "unknown psi");
-    if (p->kernel < SCMC_KERNEL_AUTO || p->kernel > SCMC_KERNEL_FUSED_PIPE)
+    if (p->kernel < SCMC_KERNEL_AUTO || p->kernel > SCMC_KERNEL_TWO_PASS_MOM)
         return bad(SCMC_EINVAL, "unknown kernel design");
     const int r = stencil_radius(p->stencil);
     if (p->lattice == SCMC_D2Q9 && p->nz != 1)
@@ -240,6 +240,10 @@ int validate(const scmc_problem *p, std::string *why) {
             return bad(SCMC_EINVAL, "tau must be finite and > 1/2");
     if (p->tau[0] != p->tau[1])
         return bad(SCMC_EUNSUPPORTED, "tau_A != tau_B is not supported");
+    if ((p->kernel == SCMC_KERNEL_FUSED_MOM || p->kernel == SCMC_KERNEL_FUSED_MOM_PIPE ||
+         p->kernel == SCMC_KERNEL_TWO_PASS_MOM) &&
+        p->tau[0] != 1.0)
+        return bad(SCMC_EUNSUPPORTED, "the moment-ring designs need tau = 1");
     for (int J = 0; J < 2; ++J)
         for (int K = 0; K < 2; ++K)
             if (!std::isfinite(p->g[J][K])) return bad(SCMC_EINVAL, "non-finite coupling");
@@ -255,9 +259,18 @@ StepKey key_of(const scmc_problem &p) {
     k.order = p.stencil;
     k.storage = p.storage;
     k.psi = p.psi_self;
-    k.repull = p.kernel == SCMC_KERNEL_FUSED_REPULL ? 1
-               : p.kernel == SCMC_KERNEL_FUSED_PIPE ? 2
-                                                    : 0;
+    switch (p.kernel) {
+        case SCMC_KERNEL_FUSED_REPULL: k.repull = 1; break;
+        case SCMC_KERNEL_FUSED_PIPE: k.repull = 2; break;
+        case SCMC_KERNEL_FUSED_MOM: k.repull = 3; break;
+        case SCMC_KERNEL_FUSED_MOM_PIPE: k.repull = 4; break;
+        case SCMC_KERNEL_AUTO: k.repull = p.tau[0] == 1.0 ? 3 : 0; break;
+        default: k.repull = 0;
+    }
+    k.mom = p.tau[0] == 1.0 && (p.kernel == SCMC_KERNEL_TWO_PASS_MOM ||
+                                p.kernel == SCMC_KERNEL_AUTO);
+    k.big = (double)lattice_q(p.lattice) * p.nx * p.ny * p.nz * storage_bytes(p.storage) >=
+            2147483648.0;
     return k;
 }
 
@@ -283,12 +296,15 @@ Member member_of(const scmc_problem &p) {
 int choose_kernel(const scmc_problem &p, const StepKey &k, int *kernel,
                   int *tile) {
     int t[3] = {p.tile[0], p.tile[1], p.tile[2]};
-    if (p.kernel == SCMC_KERNEL_TWO_PASS) {
+    // at tau = 1 the default is the moment two-pass design (the fastest
+    // untuned choice on a 128^3 sweep); the autotuner may pick a fused one
+    if (p.kernel == SCMC_KERNEL_TWO_PASS || p.kernel == SCMC_KERNEL_TWO_PASS_MOM ||
+        (p.kernel == SCMC_KERNEL_AUTO && k.mom && t[0] == 0)) {
         *kernel = SCMC_KERNEL_TWO_PASS;
         tile[0] = tile[1] = tile[2] = 0;
         return SCMC_OK;
     }
-    if (t[0] == 0) {  // default fused tile (the fastest of a 128^3 sweep)
+    if (t[0] == 0) {  // default fused tile (fits every compiled design)
         t[0] = 64;
         t[1] = 8;
         t[2] = 16;
@@ -298,12 +314,20 @@ int choose_kernel(const scmc_problem &p, const StepKey &k, int *kernel,
         for (int a = 0; a < 3; ++a) tile[a] = t[a];
         return SCMC_OK;
     }
-    if (p.kernel == SCMC_KERNEL_FUSED || p.kernel == SCMC_KERNEL_FUSED_REPULL ||
-        p.kernel == SCMC_KERNEL_FUSED_PIPE)
-        return SCMC_EUNSUPPORTED;
+    if (p.kernel != SCMC_KERNEL_AUTO) return SCMC_EUNSUPPORTED;
     *kernel = SCMC_KERNEL_TWO_PASS;
     tile[0] = tile[1] = tile[2] = 0;
     return SCMC_OK;
+}
+
+// scmc_kernel value of a resolved design
+int public_kernel(int kernel, int variant, int mom) {
+    if (kernel == SCMC_KERNEL_TWO_PASS && mom) return SCMC_KERNEL_TWO_PASS_MOM;
+    if (kernel != SCMC_KERNEL_FUSED) return kernel;
+    static const int of[] = {SCMC_KERNEL_FUSED, SCMC_KERNEL_FUSED_REPULL,
+                             SCMC_KERNEL_FUSED_PIPE, SCMC_KERNEL_FUSED_MOM,
+                             SCMC_KERNEL_FUSED_MOM_PIPE};
+    return of[variant];
 }
 
 struct Plan {
@@ -318,7 +342,7 @@ Plan plan_of(const std::vector<scmc_problem> &ps, int ntiles) {
         const size_t N = (size_t)p.nx * p.ny * p.nz;
         pop += align_up(2 * (size_t)lattice_q(p.lattice) * N *
                         storage_bytes(p.storage));
-        dens += align_up(2 * N * real_bytes(p.storage));
+        dens += align_up(5 * N * real_bytes(p.storage));
         nmax = std::max(nmax, N);
         nxmax = std::max(nxmax, (size_t)p.nx);
         nb = std::max(nb, stats_blocks(member_of(p)));
@@ -892,10 +916,7 @@ int scmc_observables(scmc_sim *s, int kind, double R0, scmc_obs *out,
 int scmc_config(scmc_sim *s, int *kernel, int *tile) {
     if (!s) return SCMC_EINVAL;
     if (kernel)
-        *kernel = s->c.kernel != SCMC_KERNEL_FUSED ? s->c.kernel
-                  : s->c.key.repull == 1            ? SCMC_KERNEL_FUSED_REPULL
-                  : s->c.key.repull == 2            ? SCMC_KERNEL_FUSED_PIPE
-                                                    : SCMC_KERNEL_FUSED;
+        *kernel = public_kernel(s->c.kernel, s->c.key.repull, s->c.key.mom);
     if (tile)
         for (int a = 0; a < 3; ++a) tile[a] = s->c.tile[a];
     return SCMC_OK;
@@ -1003,6 +1024,19 @@ static int batch_tiles(const std::vector<scmc_problem> &ps, int kernel,
     return (int)out->size();
 }
 
+// Tile-list capacity: enough for the current design, for the smallest fused
+// tile and for the two-pass tiling, so that the autotuner can switch design
+// and tile inside the same workspace.
+static int batch_tile_capacity(const std::vector<scmc_problem> &v, int kernel,
+                               const int *tile) {
+    std::vector<Tile> tiles;
+    const int tmin[3] = {32, 2, 8}, none[3] = {0, 0, 0};
+    int nt = batch_tiles(v, kernel, tile, &tiles);
+    nt = std::max(nt, batch_tiles(v, SCMC_KERNEL_FUSED, tmin, &tiles));
+    nt = std::max(nt, batch_tiles(v, SCMC_KERNEL_TWO_PASS, none, &tiles));
+    return std::max(nt, 1);
+}
+
 static int batch_check(const scmc_problem *ps, int count, std::string *why) {
     if (!ps || count < 1) return SCMC_EINVAL;
     for (int i = 0; i < count; ++i) {
@@ -1024,17 +1058,12 @@ int scmc_batch_workspace_bytes(const scmc_problem *ps, int count, size_t *out) {
     if (rc) return rc;
     std::vector<scmc_problem> v(ps, ps + count);
     int kernel, tile[3];
-    rc = choose_kernel(ps[0], key_of(ps[0]), &kernel, tile);
+    StepKey k0 = key_of(ps[0]);
+    for (int i = 1; i < count; ++i) k0.big |= key_of(ps[i]).big;
+    rc = choose_kernel(ps[0], k0, &kernel, tile);
     if (rc) return rc;
-    std::vector<Tile> tiles;
-    // the tile list is sized for the smallest candidate tile so that the
-    // autotuner can switch tiles inside the same workspace
-    int tmin[3] = {32, 2, 8};
-    const int nt = std::max(batch_tiles(v, kernel, tile, &tiles),
-                            kernel == SCMC_KERNEL_FUSED
-                                ? batch_tiles(v, kernel, tmin, &tiles)
-                                : 0);
-    *out = plan_of(v, std::max(nt, 1)).total + align_up(count * sizeof(Member));
+    const int nt = batch_tile_capacity(v, kernel, tile);
+    *out = plan_of(v, nt).total + align_up(count * sizeof(Member));
     return SCMC_OK;
 }
 
@@ -1055,20 +1084,17 @@ int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
     Common &c = b->c;
     std::vector<scmc_problem> v(ps, ps + count);
     c.key = key_of(ps[0]);
+    for (int i = 1; i < count; ++i) c.key.big |= key_of(ps[i]).big;
     rc = choose_kernel(ps[0], c.key, &c.kernel, c.tile);
     if (rc) {
         delete b;
         return rc;
     }
     std::vector<Tile> tiles;
-    int tmin[3] = {32, 2, 8};
-    const int nt_max = std::max(batch_tiles(v, c.kernel, c.tile, &tiles),
-                                c.kernel == SCMC_KERNEL_FUSED
-                                    ? batch_tiles(v, c.kernel, tmin, &tiles)
-                                    : 0);
+    const int nt_max = batch_tile_capacity(v, c.kernel, c.tile);
     b->ntiles = batch_tiles(v, c.kernel, c.tile, &tiles);
-    b->ntiles_cap = std::max(nt_max, 1);
-    const Plan pl = plan_of(v, std::max(nt_max, 1));
+    b->ntiles_cap = nt_max;
+    const Plan pl = plan_of(v, nt_max);
     c.stream = (hipStream_t)stream;
     c.ws = (char *)d_ws;
     c.ws_bytes = ws_bytes;
@@ -1093,7 +1119,7 @@ int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
         const size_t N = (size_t)L.m.N;
         pop_off += (long long)(align_up(2 * L.q * N * storage_bytes(v[i].storage)) /
                                storage_bytes(v[i].storage));
-        dens_off += (long long)(align_up(2 * N * real_bytes(v[i].storage)) /
+        dens_off += (long long)(align_up(5 * N * real_bytes(v[i].storage)) /
                                 real_bytes(v[i].storage));
         ms.push_back(L.m);
         b->lats.push_back(L);
@@ -1209,26 +1235,41 @@ int scmc_batch_config(scmc_batch *b, int *tile, int *grid) {
 namespace {
 
 struct Candidate {
-    int variant;  // StepKey::repull
+    int kernel;   // SCMC_KERNEL_FUSED or SCMC_KERNEL_TWO_PASS (internal)
+    int variant;  // StepKey::repull (fused)
+    int mom;      // StepKey::mom (two-pass)
     int tile[3];
 };
 
-// Fused candidates that this problem can run: register ring and pipelined
-// designs over the compiled tiles and three z-chunk lengths.
-std::vector<Candidate> candidates(const StepKey &k0, int nx) {
-    static const int tiles[][2] = {{64, 4}, {32, 8}, {64, 8}, {32, 16}, {128, 4}};
+// Designs this problem can run: for kernel AUTO the population-ring fused
+// designs (plain and pipelined) over the compiled tiles and three z-chunk
+// lengths and, at tau = 1, the moment-ring fused designs and the moment
+// two-pass design; for a fixed fused design, its tiles only.
+std::vector<Candidate> candidates(const scmc_problem &p, const StepKey &k0, int nx) {
+    static const int tiles[][2] = {{64, 4}, {32, 8},  {64, 8}, {32, 16},
+                                   {128, 4}, {128, 8}, {64, 16}};
     static const int chunks[] = {8, 16, 32};
+    const bool tau1 = p.tau[0] == 1.0;
+    std::vector<int> variants;
+    if (p.kernel == SCMC_KERNEL_AUTO) {
+        variants = {0, 2};
+        if (tau1) variants = {0, 2, 3, 4};
+    } else {
+        variants = {k0.repull};
+    }
     std::vector<Candidate> out;
-    for (int variant : {0, 2})
+    for (int variant : variants)
         for (const auto &t : tiles) {
             if (t[0] > 2 * nx) continue;  // mostly idle lanes
             for (int zc : chunks) {
-                Candidate c{variant, {t[0], t[1], zc}};
+                Candidate c{SCMC_KERNEL_FUSED, variant, 0, {t[0], t[1], zc}};
                 StepKey k = k0;
                 k.repull = variant;
                 if (fused_supported(k, c.tile)) out.push_back(c);
             }
         }
+    if (p.kernel == SCMC_KERNEL_AUTO && tau1)
+        out.push_back(Candidate{SCMC_KERNEL_TWO_PASS, 0, 1, {0, 0, 0}});
     return out;
 }
 
@@ -1249,8 +1290,8 @@ bool cache_lookup(const char *path, const std::string &key, Candidate *c) {
         const char *sep = strstr(line, " -> ");
         if (!sep || std::string(line, sep - line) != key) continue;
         Candidate t;
-        if (sscanf(sep + 4, "variant=%d tile=%d,%d,%d", &t.variant, &t.tile[0],
-                   &t.tile[1], &t.tile[2]) == 4) {
+        if (sscanf(sep + 4, "kernel=%d variant=%d mom=%d tile=%d,%d,%d", &t.kernel,
+                   &t.variant, &t.mom, &t.tile[0], &t.tile[1], &t.tile[2]) == 6) {
             *c = t;  // the last entry for a key wins
             found = true;
         }
@@ -1264,8 +1305,8 @@ void cache_store(const char *path, const std::string &key, const Candidate &c,
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s -> variant=%d tile=%d,%d,%d  (%.2f us/step)\n", key.c_str(),
-            c.variant, c.tile[0], c.tile[1], c.tile[2], us);
+    fprintf(f, "%s -> kernel=%d variant=%d mom=%d tile=%d,%d,%d  (%.2f us/step)\n",
+            key.c_str(), c.kernel, c.variant, c.mom, c.tile[0], c.tile[1], c.tile[2], us);
     fclose(f);
 }
 
@@ -1292,8 +1333,9 @@ int time_steps(Common &c, int warm, int steps, StepFn step, double *us) {
 }
 
 void apply(Common &c, const Candidate &cand) {
-    c.kernel = SCMC_KERNEL_FUSED;
+    c.kernel = cand.kernel;
     c.key.repull = cand.variant;
+    c.key.mom = cand.mom;
     for (int a = 0; a < 3; ++a) c.tile[a] = cand.tile[a];
     drop_graphs(c);
 }
@@ -1306,9 +1348,9 @@ int scmc_autotune(scmc_sim *s, const char *cache_path, int *tile) {
     if (!s) return SCMC_EINVAL;
     Common &c = s->c;
     const scmc_problem &p = s->lat.p;
-    if (p.kernel == SCMC_KERNEL_TWO_PASS)
+    if (p.kernel == SCMC_KERNEL_TWO_PASS || p.kernel == SCMC_KERNEL_TWO_PASS_MOM)
         return fail(c, SCMC_EUNSUPPORTED, "the two-pass design has no tile to tune");
-    std::vector<Candidate> cands = candidates(c.key, p.nx);
+    std::vector<Candidate> cands = candidates(p, c.key, p.nx);
     if (cands.empty())
         return fail(c, SCMC_EUNSUPPORTED, "no fused kernel for this problem");
     const std::string key = cache_key(p, 1);
@@ -1345,7 +1387,7 @@ int scmc_batch_autotune(scmc_batch *b, const char *cache_path, int *tile) {
     if (!b) return SCMC_EINVAL;
     Common &c = b->c;
     const scmc_problem &p0 = b->lats[0].p;
-    if (p0.kernel == SCMC_KERNEL_TWO_PASS)
+    if (p0.kernel == SCMC_KERNEL_TWO_PASS || p0.kernel == SCMC_KERNEL_TWO_PASS_MOM)
         return fail(c, SCMC_EUNSUPPORTED, "the two-pass design has no tile to tune");
     int nxmin = p0.nx;
     std::vector<scmc_problem> ps;
@@ -1353,13 +1395,13 @@ int scmc_batch_autotune(scmc_batch *b, const char *cache_path, int *tile) {
         nxmin = std::min(nxmin, L.p.nx);
         ps.push_back(L.p);
     }
-    std::vector<Candidate> cands = candidates(c.key, nxmin);
+    std::vector<Candidate> cands = candidates(p0, c.key, nxmin);
     if (cands.empty())
         return fail(c, SCMC_EUNSUPPORTED, "no fused kernel for this batch");
     const std::string key = cache_key(p0, (int)b->lats.size());
     auto use = [&](const Candidate &cand) -> int {
         std::vector<Tile> tiles;
-        const int nt = batch_tiles(ps, SCMC_KERNEL_FUSED, cand.tile, &tiles);
+        const int nt = batch_tiles(ps, cand.kernel, cand.tile, &tiles);
         if (nt > b->ntiles_cap)
             return fail(c, SCMC_ENOSPACE, "tile list larger than planned");
         apply(c, cand);

@@ -10,7 +10,8 @@ namespace scmc {
 // One lattice as the kernels see it.  Populations of a member live at
 // pop + pop_off (element offset in the storage type) in both population
 // buffers, component-major: [J][i][z][y][x]; its density field lives at
-// dens + dens_off as [J][z][y][x].
+// dens + dens_off as [J][z][y][x] (the moment two-pass: (n_A, n_B) pairs
+// [z][y][x], then the momentum planes), with room for 5 fields.
 struct Member {
     int nx, ny, nz, N;
     long long pop_off;
@@ -35,8 +36,12 @@ struct StepKey {
     int order;    // 4, 6, 8
     int storage;  // StorageKind
     int psi;      // 0 / 1
-    int repull;   // fused design: 0 = register ring, 1 = re-pull at collide,
-                  // 2 = register ring with loads issued one plane ahead
+    int repull = 0;  // fused design: 0 = register ring, 1 = re-pull at collide,
+                  // 2 = register ring with loads issued one plane ahead,
+                  // 3 / 4 = moment ring (tau = 1), plain / loads ahead
+    int mom = 0;     // two-pass design: 1 = moment passes (tau = 1)
+    int big = 0;     // 1 when a component's Q planes exceed 2^31 bytes: no
+                     // 32-bit buffer offsets (fused designs unavailable)
 };
 
 // ---- step kernels (step_kernels.hip)

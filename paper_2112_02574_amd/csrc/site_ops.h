@@ -62,14 +62,13 @@ __device__ __forceinline__ void site_density(const R (&f)[2][Lattice<D>::Q],
     nB = b;
 }
 
-// Stencil sums of eq. sc_force from a density field laid out [J][z][y][x]
-// (dA, dB), then the force on both components.
-template <int D, int ORDER, int PSI, class R>
-__device__ __forceinline__ void site_force(const Member &m,
-                                           const R *__restrict__ dA,
-                                           const R *__restrict__ dB, int x,
-                                           int y, int z, R nA, R nB, R (&FA)[3],
-                                           R (&FB)[3]) {
+// Stencil sums of eq. sc_force around site (x, y, z), with the stencil
+// concentrations returned by fetch(t, n_A, n_B) (t = linear site index), then
+// the force on both components.
+template <int D, int ORDER, int PSI, class R, class Fetch>
+__device__ __forceinline__ void site_force_fn(const Member &m, int x, int y, int z,
+                                              R nA, R nB, R (&FA)[3], R (&FB)[3],
+                                              Fetch &&fetch) {
     using S = Stencil<D, ORDER>;
     R cA[3] = {0, 0, 0}, cB[3] = {0, 0, 0};
     R sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0};
@@ -81,8 +80,9 @@ __device__ __forceinline__ void site_force(const Member &m,
         const int xs = wrap1(x + ex, m.nx);
         const int ys = wrap1(y + ey, m.ny);
         const int zs = D == 3 ? wrap1(z + ez, m.nz) : 0;
-        const long t = ((long)zs * m.ny + ys) * m.nx + xs;
-        const R nAt = dA[t], nBt = dB[t];
+        const int t = (zs * m.ny + ys) * m.nx + xs;  // N < 2^31 (validated)
+        R nAt, nBt;
+        fetch(t, nAt, nBt);
         const R W = (R)T.W[a];
         const int e3[3] = {ex, ey, ez};
 #pragma unroll
@@ -112,6 +112,20 @@ __device__ __forceinline__ void site_force(const Member &m,
         FA[k] = -gAB * nA * cA[k] - gAA * pA * sA[k];
         FB[k] = -gBA * nB * cB[k] - gBB * pB * sB[k];
     }
+}
+
+// The same from a density field laid out [J][z][y][x] (dA, dB).
+template <int D, int ORDER, int PSI, class R>
+__device__ __forceinline__ void site_force(const Member &m,
+                                           const R *__restrict__ dA,
+                                           const R *__restrict__ dB, int x,
+                                           int y, int z, R nA, R nB, R (&FA)[3],
+                                           R (&FB)[3]) {
+    site_force_fn<D, ORDER, PSI, R>(m, x, y, z, nA, nB, FA, FB,
+                                    [&](int t, R &a, R &b) {
+                                        a = dA[t];
+                                        b = dB[t];
+                                    });
 }
 
 // Common velocity, BGK collision with Guo forcing; every f*_i^J is handed to
@@ -154,6 +168,74 @@ __device__ __forceinline__ void site_collide(const Member &m,
             const R S = w * (R(3) * xF + R(9) * xu * xF - R(3) * uF);
             const R out = f[J][i] - omega * (f[J][i] - feq) + cf * S;
             sink(J, i, out, w * n0[J]);
+        }
+    }
+}
+
+// Moments that the collision needs at omega = 1: n_J and the total momentum
+// j = sum_J sum_i f_i^J xi_i.
+template <int D, class R>
+__device__ __forceinline__ void site_moments(const R (&f)[2][Lattice<D>::Q],
+                                             R (&mom)[5]) {
+    using L = Lattice<D>;
+    R nA = 0, nB = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        nA += f[0][i];
+        nB += f[1][i];
+        const R t = f[0][i] + f[1][i];
+        if (L::CX[i]) jx += (R)L::CX[i] * t;
+        if (L::CY[i]) jy += (R)L::CY[i] * t;
+        if (D == 3 && L::CZ[i]) jz += (R)L::CZ[i] * t;
+    }
+    mom[0] = nA;
+    mom[1] = nB;
+    mom[2] = jx;
+    mom[3] = jy;
+    mom[4] = jz;
+}
+
+// The collision at omega = 1 (tau = 1), where f* = f^eq(n_J, u) + S_i / 2
+// no longer depends on the individual pre-collision populations.  With
+// a_J = n_J (1 - 3/2 u.u) - 3/2 u.F_J, a velocity xi and its opposite share
+//   E = w [a_J + 9/2 (xi.u) (n_J xi.u + xi.F_J)]
+// and differ in the sign of
+//   O = w [3 n_J xi.u + 3/2 xi.F_J],   f*_xi = E + O, f*_-xi = E - O.
+// Every f*_i^J goes to sink(J, i, value, w_i n0_J).
+template <int D, class R, class Sink>
+__device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[5],
+                                             const R (&FA)[3], const R (&FB)[3],
+                                             Sink &&sink) {
+    using L = Lattice<D>;
+    const R nA = mom[0], nB = mom[1];
+    const R inv = R(1) / (nA + nB);
+    const R ux = (mom[2] + R(0.5) * (FA[0] + FB[0])) * inv;
+    const R uy = (mom[3] + R(0.5) * (FA[1] + FB[1])) * inv;
+    const R uz = D == 3 ? (mom[4] + R(0.5) * (FA[2] + FB[2])) * inv : R(0);
+    const R uu = ux * ux + uy * uy + uz * uz;
+    const R n0[2] = {(R)m.n0[0], (R)m.n0[1]};
+    constexpr Opposite<D> OP = Opposite<D>::make();
+#pragma unroll
+    for (int J = 0; J < 2; ++J) {
+        const R *F = J == 0 ? FA : FB;
+        const R nJ = J == 0 ? nA : nB;
+        const R uF = ux * F[0] + uy * F[1] + uz * F[2];
+        const R a = nJ * (R(1) - R(1.5) * uu) - R(1.5) * uF;
+        sink(J, 0, (R)L::W[0] * a, (R)L::W[0] * n0[J]);
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const int ib = OP.opp[i];
+            if (ib < i) continue;
+            R xu = 0, xF = 0;
+            if (L::CX[i]) { xu += (R)L::CX[i] * ux; xF += (R)L::CX[i] * F[0]; }
+            if (L::CY[i]) { xu += (R)L::CY[i] * uy; xF += (R)L::CY[i] * F[1]; }
+            if (D == 3 && L::CZ[i]) { xu += (R)L::CZ[i] * uz; xF += (R)L::CZ[i] * F[2]; }
+            const R w = (R)L::W[i];
+            const R t = nJ * xu;
+            const R E = w * (a + R(4.5) * xu * (t + xF));
+            const R O = w * (R(3) * t + R(1.5) * xF);
+            sink(J, i, E + O, w * n0[J]);
+            sink(J, ib, E - O, w * n0[J]);
         }
     }
 }

@@ -9,6 +9,15 @@
 // 64 consecutive x, so every pull of every direction is one coalesced row
 // segment.  This design handles every lattice, stencil and storage format and
 // is the reference path of the fused kernels.
+//
+// At tau = 1 the second pass need not pull again: the collision then depends
+// on the populations only through n_J and the total momentum j.  Pass 1
+// (k_moments) stores (n_A, n_B) pairs followed by the j planes; pass 2
+// (k_collide_mom) reads the node's moments and the stencil's concentration
+// pairs and stores f*.  Per site it moves 2Q reads + 2Q writes of populations
+// plus (2 + d) moment writes and reads, instead of 4Q reads + 2Q writes.
+#include <type_traits>
+
 #include "site_ops.h"
 
 namespace scmc {
@@ -52,6 +61,199 @@ __global__ void __launch_bounds__(256)
     site_force<D, ORDER, PSI, R>(m, dA, dA + m.N, x, y, z, nA, nB, FA, FB);
     const long s = ((long)z * m.ny + y) * m.nx + x;
     site_collide_store<D, ST>(m, f, nA, nB, FA, FB, dst, s);
+}
+
+// ---- tau = 1: moment two-pass
+template <class R> using Pair = typename std::conditional<std::is_same<R, float>::value,
+                                                          float2, double2>::type;
+
+// moment field of a member: (n_A, n_B) pairs [z][y][x], then j_x, j_y (, j_z)
+template <int D, class ST>
+__device__ __forceinline__ void moments_site(const Member &m,
+                                             const typename ST::T *__restrict__ src,
+                                             typename ST::R *__restrict__ mom, int x,
+                                             int y, int z) {
+    using R = typename ST::R;
+    R f[2][Lattice<D>::Q], mm[5];
+    pull_site<D, ST>(m, src, x, y, z, f);
+    site_moments<D, R>(f, mm);
+    const long s = ((long)z * m.ny + y) * m.nx + x;
+    R *base = mom + m.dens_off;
+    Pair<R> pr;
+    pr.x = mm[0];
+    pr.y = mm[1];
+    reinterpret_cast<Pair<R> *>(base)[s] = pr;
+#pragma unroll
+    for (int c = 0; c < D; ++c) base[(2 + c) * (long)m.N + s] = mm[2 + c];
+}
+
+template <int D, int ORDER, class ST, int PSI>
+__device__ __forceinline__ void collide_mom_site(const Member &m,
+                                                 typename ST::T *__restrict__ dst,
+                                                 const typename ST::R *__restrict__ mom,
+                                                 int x, int y, int z) {
+    using R = typename ST::R;
+    const R *base = mom + m.dens_off;
+    const Pair<R> *pairs = reinterpret_cast<const Pair<R> *>(base);
+    const long s = ((long)z * m.ny + y) * m.nx + x;
+    const Pair<R> own = pairs[s];
+    R mm[5] = {own.x, own.y, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < D; ++c) mm[2 + c] = base[(2 + c) * (long)m.N + s];
+    R FA[3], FB[3];
+    site_force_fn<D, ORDER, PSI, R>(m, x, y, z, own.x, own.y, FA, FB,
+                                    [&](int t, R &a, R &b) {
+                                        const Pair<R> q = pairs[t];
+                                        a = q.x;
+                                        b = q.y;
+                                    });
+    typename ST::T *out = dst + m.pop_off;
+    collide_tau1<D, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
+        ST::store(out, (long)(J * Lattice<D>::Q + i) * m.N + s, v, ref);
+    });
+}
+
+// D3Q19 forms with 32-bit buffer offsets (each component's Q planes below
+// 2 GiB): plane offsets go in the scalar offset, lanes carry 32-bit offsets.
+template <class ST>
+__device__ __forceinline__ void moments_site_buf(const Member &m, const PopBuf<ST> &sb,
+                                                 typename ST::R *__restrict__ mom, int x,
+                                                 int y, int z) {
+    using R = typename ST::R;
+    R f[2][19], mm[5];
+    pull_site_buf<ST>(m, sb, x, y, z, f);
+    site_moments<3, R>(f, mm);
+    const int s = (z * m.ny + y) * m.nx + x;
+    R *base = mom + m.dens_off;
+    reinterpret_cast<Pair<R> *>(base)[s] = Pair<R>{mm[0], mm[1]};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) base[(2 + c) * (long)m.N + s] = mm[2 + c];
+}
+
+template <int ORDER, class ST, int PSI>
+__device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopBuf<ST> &db,
+                                                     const typename ST::R *__restrict__ mom,
+                                                     int x, int y, int z) {
+    using R = typename ST::R;
+    using T = typename ST::T;
+    const R *base = mom + m.dens_off;
+    const Pair<R> *pairs = reinterpret_cast<const Pair<R> *>(base);
+    const int s = (z * m.ny + y) * m.nx + x;
+    const Pair<R> own = pairs[s];
+    R mm[5] = {own.x, own.y, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mm[2 + c] = base[(2 + c) * (long)m.N + s];
+    R FA[3], FB[3];
+    site_force_fn<3, ORDER, PSI, R>(m, x, y, z, own.x, own.y, FA, FB,
+                                    [&](int t, R &a, R &b) {
+                                        const Pair<R> q = pairs[t];
+                                        a = q.x;
+                                        b = q.y;
+                                    });
+    const int voff = s * (int)sizeof(T);
+    collide_tau1<3, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
+        RawBuf<T>::store_nt(ST::to_raw(v, ref), db.r[J], voff, i * db.plane_bytes);
+    });
+}
+
+template <class ST>
+__global__ void __launch_bounds__(256)
+    k_moments_buf(Member m, const typename ST::T *__restrict__ src,
+                  typename ST::R *__restrict__ mom) {
+    const int x = blockIdx.x * TP_BX + threadIdx.x;
+    const int y = blockIdx.y * TP_BY + threadIdx.y;
+    const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
+    if (x < m.nx && y < m.ny) moments_site_buf<ST>(m, sb, mom, x, y, blockIdx.z);
+}
+
+template <int ORDER, class ST, int PSI>
+__global__ void __launch_bounds__(256)
+    k_collide_mom_buf(Member m, const typename ST::T *__restrict__ src,
+                      typename ST::T *__restrict__ dst,
+                      const typename ST::R *__restrict__ mom) {
+    const int x = blockIdx.x * TP_BX + threadIdx.x;
+    const int y = blockIdx.y * TP_BY + threadIdx.y;
+    const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
+    if (x < m.nx && y < m.ny)
+        collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, blockIdx.z);
+}
+
+template <class ST>
+__global__ void __launch_bounds__(256)
+    kb_moments_buf(const Member *__restrict__ members, const Tile *__restrict__ tiles,
+                   int ntiles, const typename ST::T *__restrict__ src,
+                   typename ST::R *__restrict__ mom) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        const Member m = members[tl.member];
+        const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
+        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y;
+        if (x < m.nx && y < m.ny) moments_site_buf<ST>(m, sb, mom, x, y, tl.z0);
+    }
+}
+
+template <int ORDER, class ST, int PSI>
+__global__ void __launch_bounds__(256)
+    kb_collide_mom_buf(const Member *__restrict__ members, const Tile *__restrict__ tiles,
+                       int ntiles, const typename ST::T *__restrict__ src,
+                       typename ST::T *__restrict__ dst,
+                       const typename ST::R *__restrict__ mom) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        const Member m = members[tl.member];
+        const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
+        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y;
+        if (x < m.nx && y < m.ny)
+            collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, tl.z0);
+    }
+}
+
+template <int D, class ST>
+__global__ void __launch_bounds__(256)
+    k_moments(Member m, const typename ST::T *__restrict__ src,
+              typename ST::R *__restrict__ mom) {
+    const int x = blockIdx.x * TP_BX + threadIdx.x;
+    const int y = blockIdx.y * TP_BY + threadIdx.y;
+    if (x < m.nx && y < m.ny) moments_site<D, ST>(m, src, mom, x, y, blockIdx.z);
+}
+
+template <int D, int ORDER, class ST, int PSI>
+__global__ void __launch_bounds__(256)
+    k_collide_mom(Member m, const typename ST::T *__restrict__ src,
+                  typename ST::T *__restrict__ dst,
+                  const typename ST::R *__restrict__ mom) {
+    const int x = blockIdx.x * TP_BX + threadIdx.x;
+    const int y = blockIdx.y * TP_BY + threadIdx.y;
+    if (x < m.nx && y < m.ny)
+        collide_mom_site<D, ORDER, ST, PSI>(m, dst, mom, x, y, blockIdx.z);
+}
+
+template <int D, class ST>
+__global__ void __launch_bounds__(256)
+    kb_moments(const Member *__restrict__ members, const Tile *__restrict__ tiles,
+               int ntiles, const typename ST::T *__restrict__ src,
+               typename ST::R *__restrict__ mom) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        const Member m = members[tl.member];
+        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y;
+        if (x < m.nx && y < m.ny) moments_site<D, ST>(m, src, mom, x, y, tl.z0);
+    }
+}
+
+template <int D, int ORDER, class ST, int PSI>
+__global__ void __launch_bounds__(256)
+    kb_collide_mom(const Member *__restrict__ members, const Tile *__restrict__ tiles,
+                   int ntiles, const typename ST::T *__restrict__ src,
+                   typename ST::T *__restrict__ dst,
+                   const typename ST::R *__restrict__ mom) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        const Member m = members[tl.member];
+        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y;
+        if (x < m.nx && y < m.ny)
+            collide_mom_site<D, ORDER, ST, PSI>(m, dst, mom, x, y, tl.z0);
+    }
 }
 
 // ---- batched forms: a persistent grid walks a tile list; a tile is a
@@ -139,6 +341,11 @@ static bool dispatch_shape(const StepKey &k, F &&fn) {
     return false;
 }
 
+// the 32-bit buffer forms serve D3Q19 with FP32-compute storage that fits
+template <int D, class ST> constexpr bool buf_form() {
+    return D == 3 && !std::is_same<ST, StoreF64>::value;
+}
+
 static dim3 tp_grid(const Member &m) {
     return dim3((m.nx + TP_BX - 1) / TP_BX, (m.ny + TP_BY - 1) / TP_BY, m.nz);
 }
@@ -155,10 +362,28 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
             constexpr int O = decltype(Oc)::value;
             constexpr int P = decltype(Pc)::value;
             const dim3 g = tp_grid(m), b(TP_BX, TP_BY, 1);
-            hipLaunchKernelGGL((k_density<D, ST>), g, b, 0, st, m,
-                               (const T *)src, (R *)dens);
-            hipLaunchKernelGGL((k_collide<D, O, ST, P>), g, b, 0, st, m,
-                               (const T *)src, (T *)dst, (const R *)dens);
+            bool done = false;
+            if constexpr (buf_form<D, ST>()) {
+                if (k.mom && !k.big) {
+                    hipLaunchKernelGGL((k_moments_buf<ST>), g, b, 0, st, m,
+                                       (const T *)src, (R *)dens);
+                    hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P>), g, b, 0, st, m,
+                                       (const T *)src, (T *)dst, (const R *)dens);
+                    done = true;
+                }
+            }
+            if (done) {
+            } else if (k.mom) {
+                hipLaunchKernelGGL((k_moments<D, ST>), g, b, 0, st, m,
+                                   (const T *)src, (R *)dens);
+                hipLaunchKernelGGL((k_collide_mom<D, O, ST, P>), g, b, 0, st, m,
+                                   (const T *)src, (T *)dst, (const R *)dens);
+            } else {
+                hipLaunchKernelGGL((k_density<D, ST>), g, b, 0, st, m,
+                                   (const T *)src, (R *)dens);
+                hipLaunchKernelGGL((k_collide<D, O, ST, P>), g, b, 0, st, m,
+                                   (const T *)src, (T *)dst, (const R *)dens);
+            }
             err = hipGetLastError();
         });
     });
@@ -174,8 +399,15 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dn, NodeLaunch *sn,
             constexpr int D = decltype(Dc)::value;
             constexpr int O = decltype(Oc)::value;
             constexpr int P = decltype(Pc)::value;
-            dn->func = (void *)&k_density<D, ST>;
-            sn->func = (void *)&k_collide<D, O, ST, P>;
+            dn->func = k.mom ? (void *)&k_moments<D, ST> : (void *)&k_density<D, ST>;
+            sn->func = k.mom ? (void *)&k_collide_mom<D, O, ST, P>
+                             : (void *)&k_collide<D, O, ST, P>;
+            if constexpr (buf_form<D, ST>()) {
+                if (k.mom && !k.big) {
+                    dn->func = (void *)&k_moments_buf<ST>;
+                    sn->func = (void *)&k_collide_mom_buf<O, ST, P>;
+                }
+            }
             dn->grid = sn->grid = tp_grid(m);
             dn->block = sn->block = dim3(TP_BX, TP_BY, 1);
             dn->shmem = sn->shmem = 0;
@@ -199,12 +431,34 @@ hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
             constexpr int O = decltype(Oc)::value;
             constexpr int P = decltype(Pc)::value;
             const dim3 b(TP_BX, TP_BY, 1);
-            hipLaunchKernelGGL((kb_density<D, ST>), dim3(grid), b, 0, st,
-                               d_members, d_tiles, ntiles, (const T *)src,
-                               (R *)dens);
-            hipLaunchKernelGGL((kb_collide<D, O, ST, P>), dim3(grid), b, 0,
-                               st, d_members, d_tiles, ntiles, (const T *)src,
-                               (T *)dst, (const R *)dens);
+            bool done = false;
+            if constexpr (buf_form<D, ST>()) {
+                if (k.mom && !k.big) {
+                    hipLaunchKernelGGL((kb_moments_buf<ST>), dim3(grid), b, 0, st,
+                                       d_members, d_tiles, ntiles, (const T *)src,
+                                       (R *)dens);
+                    hipLaunchKernelGGL((kb_collide_mom_buf<O, ST, P>), dim3(grid), b, 0,
+                                       st, d_members, d_tiles, ntiles, (const T *)src,
+                                       (T *)dst, (const R *)dens);
+                    done = true;
+                }
+            }
+            if (done) {
+            } else if (k.mom) {
+                hipLaunchKernelGGL((kb_moments<D, ST>), dim3(grid), b, 0, st,
+                                   d_members, d_tiles, ntiles, (const T *)src,
+                                   (R *)dens);
+                hipLaunchKernelGGL((kb_collide_mom<D, O, ST, P>), dim3(grid), b, 0,
+                                   st, d_members, d_tiles, ntiles, (const T *)src,
+                                   (T *)dst, (const R *)dens);
+            } else {
+                hipLaunchKernelGGL((kb_density<D, ST>), dim3(grid), b, 0, st,
+                                   d_members, d_tiles, ntiles, (const T *)src,
+                                   (R *)dens);
+                hipLaunchKernelGGL((kb_collide<D, O, ST, P>), dim3(grid), b, 0,
+                                   st, d_members, d_tiles, ntiles, (const T *)src,
+                                   (T *)dst, (const R *)dens);
+            }
             err = hipGetLastError();
         });
     });
@@ -220,8 +474,15 @@ bool node_batch_two_pass(const StepKey &k, int grid, NodeLaunch *dn,
             constexpr int D = decltype(Dc)::value;
             constexpr int O = decltype(Oc)::value;
             constexpr int P = decltype(Pc)::value;
-            dn->func = (void *)&kb_density<D, ST>;
-            sn->func = (void *)&kb_collide<D, O, ST, P>;
+            dn->func = k.mom ? (void *)&kb_moments<D, ST> : (void *)&kb_density<D, ST>;
+            sn->func = k.mom ? (void *)&kb_collide_mom<D, O, ST, P>
+                             : (void *)&kb_collide<D, O, ST, P>;
+            if constexpr (buf_form<D, ST>()) {
+                if (k.mom && !k.big) {
+                    dn->func = (void *)&kb_moments_buf<ST>;
+                    sn->func = (void *)&kb_collide_mom_buf<O, ST, P>;
+                }
+            }
             dn->grid = sn->grid = dim3(grid);
             dn->block = sn->block = dim3(TP_BX, TP_BY, 1);
             dn->shmem = sn->shmem = 0;

@@ -21,6 +21,7 @@ E4, E6, E8 = 4, 6, 8
 PSI_N, PSI_EXP_NEG_INV = 0, 1
 F64, F32, F16_OFF, BF16_OFF = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_TWO_PASS, KERNEL_FUSED, KERNEL_FUSED_REPULL, KERNEL_FUSED_PIPE = 0, 1, 2, 3, 4
+KERNEL_FUSED_MOM, KERNEL_FUSED_MOM_PIPE, KERNEL_TWO_PASS_MOM = 5, 6, 7
 OBS_FLAT, OBS_DROPLET = 0, 1
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16_OFF: "f16", BF16_OFF: "bf16"}
 

@@ -8,7 +8,11 @@ library.  Usage (repository root):
     python tests/golden/make_golden.py c2      # 4 x 256^2 droplets, 20000 steps
     python tests/golden/make_golden.py c3      # 128^3 droplet, 30000 steps
 
-Each writes tests/golden/<name>_oracle.json.
+Each writes tests/golden/<name>_oracle.json.  The droplet cases start the way
+Sec. 4 does: a flat interface with the same couplings is relaxed first (the
+oracle's ``flat_equilibrium``) and the droplet's tanh profile then joins its
+two bulk concentrations; the stored ``bulk`` values let a checked run start
+from the identical fields.  ORACLE_THREADS sets the OpenMP threads.
 """
 import json
 import os
@@ -23,6 +27,17 @@ from paper_2112_02574_amd import inputs  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 G_SYM = ((0.0, 1.8), (1.8, 0.0))
+THREADS = int(os.environ.get("ORACLE_THREADS", "0"))
+
+
+def flat_bulk(dim, order, g, lx=128):
+    """Stage one of the Sec. 4 initialisation, on the oracle."""
+    t0 = time.time()
+    bulk, steps = O.flat_equilibrium(dim, order, g, lx=lx, guess=inputs.FLAT_GUESS[g[0][0]],
+                                     tol=1e-10, nthreads=1)
+    print(f"flat stage d={dim} E{order}: {bulk} after {steps} steps ({time.time() - t0:.0f} s)",
+          flush=True)
+    return bulk, steps
 
 
 def _write(name, payload):
@@ -52,11 +67,12 @@ def c1():
 def c2():
     """D2Q9, E8, 256x256, four A-rich droplets R0 in {12, 20, 32, 48};
     20000 steps.  Droplet observables (2D forms)."""
-    out = {"steps": 20000, "members": []}
+    bulk, fsteps = flat_bulk(2, 8, G_SYM)
+    out = {"steps": 20000, "bulk": bulk, "flat_steps": fsteps, "flat_lx": 128, "members": []}
     for R0 in (12.0, 20.0, 32.0, 48.0):
         t0 = time.time()
-        o = O.Oracle(2, 8, (256, 256), tau=1.0, g=G_SYM)
-        o.set_density(*inputs.droplet(256, 256, R=R0))
+        o = O.Oracle(2, 8, (256, 256), tau=1.0, g=G_SYM, nthreads=THREADS)
+        o.set_density(*inputs.droplet(256, 256, R=R0, bulk=bulk))
         o.run(20000)
         d = o.droplet_observables(R0)
         d = {k: (v.tolist() if hasattr(v, "tolist") else v) for k, v in d.items()}
@@ -72,8 +88,9 @@ def c3(steps=30000, every=2048):
     """D3Q19, E6, 128^3 droplet R0 = 24, tau = 1, g_AB = 1.8; observables every
     2048 steps (the paper's monitoring interval) and at the end."""
     L, R0 = 128, 24.0
-    o = O.Oracle(3, 6, (L, L, L), tau=1.0, g=G_SYM, nthreads=int(os.environ.get("ORACLE_THREADS", "0")))
-    o.set_density(*inputs.droplet(L, L, L, R=R0))
+    bulk, fsteps = flat_bulk(3, 6, G_SYM)
+    o = O.Oracle(3, 6, (L, L, L), tau=1.0, g=G_SYM, nthreads=THREADS)
+    o.set_density(*inputs.droplet(L, L, L, R=R0, bulk=bulk))
     hist = []
     done = 0
     t0 = time.time()
@@ -92,7 +109,8 @@ def c3(steps=30000, every=2048):
     n = o.density()
     final["nA_axis"] = n[0, L // 2, L // 2, :].tolist()
     final["nB_axis"] = n[1, L // 2, L // 2, :].tolist()
-    _write("c3", {"steps": steps, "history": hist, "final": final})
+    _write("c3", {"steps": steps, "bulk": bulk, "flat_steps": fsteps, "flat_lx": 128,
+                  "history": hist, "final": final})
 
 
 if __name__ == "__main__":

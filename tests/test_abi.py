@@ -66,7 +66,9 @@ def test_workspace_planner():
     (lambda p: p.g[0].__setitem__(0, float("nan")), -1),
     (lambda p: setattr(p, "storage", 9), -1),
     (lambda p: setattr(p, "psi_self", 3), -1),
-    (lambda p: setattr(p, "kernel", 5), -1),
+    (lambda p: setattr(p, "kernel", 8), -1),
+    (lambda p: (setattr(p, "kernel", scmc.KERNEL_FUSED_MOM), p.tau.__setitem__(0, 0.8),
+                p.tau.__setitem__(1, 0.8)), -2),          # moment ring needs tau = 1
 ])
 def test_invalid_problems(mutate, status):
     p = scmc.problem(scmc.D3Q19, scmc.E6, (16, 16, 16))

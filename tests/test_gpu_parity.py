@@ -10,6 +10,8 @@ storage precision, unit roundoff u, over the number of steps run):
     significant bits of |f - w n0| <= w * 0.5; a single step is checked to
     half an ulp of the largest offset, longer runs are reported elsewhere.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -52,7 +54,8 @@ def _oracle_for(lattice, stencil, shape, psi, g, tau=1.0):
     return O.Oracle(dim, stencil, shape, tau=tau, g=g, psi_self=psi)
 
 
-@pytest.mark.parametrize("kernel", [scmc.KERNEL_TWO_PASS, scmc.KERNEL_AUTO])
+@pytest.mark.parametrize("kernel", [scmc.KERNEL_TWO_PASS, scmc.KERNEL_AUTO,
+                                    scmc.KERNEL_TWO_PASS_MOM, scmc.KERNEL_FUSED_MOM])
 @pytest.mark.parametrize("storage,tol,steps", [(scmc.F64, 1e-12, 25), (scmc.F32, 2e-6, 25)])
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_populations_match_oracle(case, storage, tol, steps, kernel):
@@ -60,6 +63,10 @@ def test_populations_match_oracle(case, storage, tol, steps, kernel):
     print(f"case {case} storage {storage} kernel {kernel} shape {shape}", flush=True)
     nA, nB = _random_state(shape, 100 + case)
     tau = 0.8 if case % 2 else 1.0
+    if kernel in (scmc.KERNEL_TWO_PASS_MOM, scmc.KERNEL_FUSED_MOM) and tau != 1.0:
+        pytest.skip("moment designs need tau = 1")
+    if kernel == scmc.KERNEL_FUSED_MOM and (lattice == scmc.D2Q9 or storage == scmc.F64):
+        pytest.skip("fused designs are D3Q19 with FP32-compute storage")
     p = scmc.problem(lattice, stencil, shape, tau=tau, g=g, psi_self=psi, storage=storage,
                      kernel=kernel)
     sim = scmc.Sim(p)
@@ -268,6 +275,8 @@ def test_full_size_sampled_single_step():
     nA, nB = inputs.droplet(L, L, L, R=R0)
     p = scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), storage=scmc.F32)
     sim = scmc.Sim(p)
+    # the design and tile the benchmark runs (same tuner and cache file)
+    sim.scmc_autotune(os.path.join(os.environ.get("TMPDIR", "/tmp"), "scmc_autotune.txt"))
     sim.scmc_set_density(nA, nB)
     sim.scmc_step(1)
     f1, _ = sim.scmc_get_populations()
@@ -291,7 +300,10 @@ def test_full_size_sampled_single_step():
 @pytest.mark.parametrize("kernel,tile", [
     (scmc.KERNEL_FUSED, (128, 4, 8)), (scmc.KERNEL_FUSED, (32, 16, 16)),
     (scmc.KERNEL_FUSED, (64, 4, 32)), (scmc.KERNEL_FUSED_REPULL, (64, 8, 16)),
-    (scmc.KERNEL_FUSED_PIPE, (32, 8, 16)), (scmc.KERNEL_FUSED_PIPE, (64, 8, 8))])
+    (scmc.KERNEL_FUSED_PIPE, (32, 8, 16)), (scmc.KERNEL_FUSED_PIPE, (64, 8, 8)),
+    (scmc.KERNEL_FUSED_MOM, (64, 8, 16)), (scmc.KERNEL_FUSED_MOM, (128, 8, 8)),
+    (scmc.KERNEL_FUSED_MOM, (64, 16, 32)), (scmc.KERNEL_FUSED_MOM, (32, 8, 8)),
+    (scmc.KERNEL_FUSED_MOM_PIPE, (32, 8, 16)), (scmc.KERNEL_FUSED_MOM_PIPE, (64, 8, 8))])
 @pytest.mark.parametrize("stencil", [scmc.E4, scmc.E6])
 def test_fused_designs_match_two_pass(kernel, tile, stencil):
     """Every fused design and tile (ragged x, y and z chunks included) gives
@@ -324,7 +336,8 @@ def test_autotune_picks_a_working_design(tmp_path):
     tile = s.scmc_autotune(cache)
     kernel, t2 = s.scmc_config()
     assert t2 == tile and kernel in (scmc.KERNEL_FUSED, scmc.KERNEL_FUSED_REPULL,
-                                     scmc.KERNEL_FUSED_PIPE)
+                                     scmc.KERNEL_FUSED_PIPE, scmc.KERNEL_FUSED_MOM,
+                                     scmc.KERNEL_FUSED_MOM_PIPE, scmc.KERNEL_TWO_PASS_MOM)
     assert open(cache).read().count("->") == 1
     with pytest.raises(scmc.ScmcError):   # the tuner's scratch state is not kept
         s.scmc_step(1)
