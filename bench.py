@@ -28,6 +28,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -317,6 +319,106 @@ def run(args):
     print(json.dumps(line), flush=True)
 
 
+def precision_study(args, out_md):
+    """256^3 D3Q19 / E6 B-rich droplet, R0 = 64, g_AB = 1.8, g_AA = -0.2, psi = n:
+    the same run with populations stored in FP64, FP32, FP16 offsets and BF16
+    offsets (FP32 arithmetic for the last three), observables every 2^11 steps.
+    FP64 storage stands in for the oracle at this size (its parity with the
+    oracle is tested on smaller lattices); errors are stated against it."""
+    import torch
+
+    from paper_2112_02574_amd import inputs
+    from paper_2112_02574_amd import scmc
+
+    L, R0 = args.size, args.size / 4.0
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    bulk, flat_steps = scmc.scmc_flat_equilibrium(
+        scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), g=G_ASYM, storage=scmc.F64),
+        lx=128, guess=inputs.FLAT_GUESS[-0.2], tol=1e-10, device=dev, stream=stream)
+    init = inputs.droplet(L, L, L, R=R0, a_rich=False, bulk=bulk)
+    n0 = (0.5 * (bulk[0] + bulk[2]), 0.5 * (bulk[1] + bulk[3]))
+    runs = {}
+    for name, storage in (("f64", scmc.F64), ("f32", scmc.F32), ("f16_offset", scmc.F16_OFF),
+                          ("bf16_offset", scmc.BF16_OFF)):
+        sim = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), g=G_ASYM, storage=storage,
+                                    n0=n0), device=dev, stream=stream)
+        if storage != scmc.F64:
+            sim.scmc_autotune(args.tune_cache)
+        sim.scmc_set_density(*init)
+        hist, step_ms, done = [], 0.0, 0
+        while done < args.steps:
+            k = min(OBS_EVERY, args.steps - done)
+            step_ms += _timed_chunk(sim.scmc_step, k, stream)
+            done += k
+            o = sim.scmc_observables(scmc.OBS_DROPLET, R0)
+            st = sim.scmc_stats_get()
+            hist.append({"step": done, "dP": _finite(o["dP"]), "R_s": _finite(o["R_s"]),
+                         "sigma_s": _finite(o["sigma_s"]), "max_u": _finite(st["max_u"]),
+                         "mass": st["mass"].tolist()})
+            print(f"{name} step {done}: dP={o['dP']:.6g} R_s={o['R_s']:.6g} "
+                  f"sigma_s={o['sigma_s']:.6g}", flush=True)
+        nA, nB = sim.scmc_get_fields()
+        kernel, tile = sim.scmc_config()
+        runs[name] = {"hist": hist, "MLUPS": round(L ** 3 * done / (step_ms * 1e3), 1),
+                      "kernel": KERNEL_NAMES[kernel], "tile": list(tile),
+                      "axis_nA": nA[L // 2, L // 2, :].copy(), "axis_nB": nB[L // 2, L // 2, :].copy()}
+        sim.close()
+    ref = runs["f64"]
+    lines = ["# Storage precision on a 256^3 asymmetric droplet", "",
+             "D3Q19, E6, 256^3 periodic, B-rich droplet R0 = 64 between the flat-interface bulk "
+             "values (flat stage on 128 x 5 x 5, FP64: nA_in, nB_in, nA_out, nB_out = %s), tau = 1, "
+             "g_AB = 1.8, g_AA = -0.2, g_BB = 0, psi = n; n0 = %s (midpoints of the bulk values). "
+             "%d steps per run, observables every 2^11 steps. FP64 storage is the reference "
+             "(its parity with the oracle is tested on smaller lattices)." % (
+                 [round(v, 9) for v in bulk], [round(v, 6) for v in n0], args.steps), "",
+             "Command (repository root, one MI355X):", "",
+             "    python bench.py --precision profiles/precision_256cube_asym.md --size %d --steps %d"
+             % (L, args.steps), "",
+             "| storage | design | MLUPS | dP | R_s | sigma_s | abs err R_s | rel err sigma_s | "
+             "max abs err n on axis |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    out = {"workload": f"D3Q19 E6 {L}^3 B-rich droplet R0={R0:g} g_AA=-0.2", "steps": args.steps,
+           "bulk": bulk.tolist() if hasattr(bulk, "tolist") else list(bulk), "runs": {}}
+    for name, r in runs.items():
+        f = r["hist"][-1]
+        g = ref["hist"][-1]
+        eR = abs(f["R_s"] - g["R_s"]) if f["R_s"] is not None and g["R_s"] is not None else None
+        es = (abs(f["sigma_s"] - g["sigma_s"]) / abs(g["sigma_s"])
+              if f["sigma_s"] is not None and g["sigma_s"] else None)
+        en = float(max(np.abs(r["axis_nA"] - ref["axis_nA"]).max(),
+                       np.abs(r["axis_nB"] - ref["axis_nB"]).max()))
+        lines.append("| %s | %s | %.0f | %s | %s | %s | %s | %s | %.3g |" % (
+            name, r["kernel"], r["MLUPS"], _fmt(f["dP"], "%.8g"), _fmt(f["R_s"], "%.8g"),
+            _fmt(f["sigma_s"], "%.8g"), _fmt(eR, "%.3g"), _fmt(es, "%.3g"), en))
+        out["runs"][name] = {"MLUPS": r["MLUPS"], "kernel": r["kernel"], "final": f,
+                             "abs_err_R_s": eR, "rel_err_sigma_s": es, "max_abs_err_n_axis": en,
+                             "history": r["hist"]}
+    lines += ["", "History of R_s (every 2^11 steps):", "",
+              "| step | " + " | ".join(runs) + " |", "|---|" + "---|" * len(runs)]
+    for i, h in enumerate(ref["hist"]):
+        lines.append("| %d | " % h["step"] + " | ".join(
+            _fmt(runs[n]["hist"][i]["R_s"], "%.6g") for n in runs) + " |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps(out), flush=True)
+
+
+def _fmt(v, f):
+    return f % v if v is not None else "-"
+
+
+def _timed_chunk(step, k, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    step(k)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,9 +443,15 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (torch copy_), the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--precision", metavar="OUT_MD", default=None,
+                    help="only run the storage-precision study (256^3 asymmetric droplet; "
+                         "use --size 256 --steps N) and write its summary to OUT_MD")
     ap.add_argument("--summarize", metavar="DIR", default=None,
                     help="only write the profiles/ summaries from rocprofv3 output in DIR")
     args = ap.parse_args()
+    if args.precision:
+        precision_study(args, args.precision)
+        return
     if args.summarize:
         summarize_profiles(args.summarize, args.size)
         return

@@ -160,8 +160,8 @@ template <class ST>
 __global__ void __launch_bounds__(256)
     k_moments_buf(Member m, const typename ST::T *__restrict__ src,
                   typename ST::R *__restrict__ mom) {
-    const int x = blockIdx.x * TP_BX + threadIdx.x;
-    const int y = blockIdx.y * TP_BY + threadIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
     if (x < m.nx && y < m.ny) moments_site_buf<ST>(m, sb, mom, x, y, blockIdx.z);
 }
@@ -171,8 +171,8 @@ __global__ void __launch_bounds__(256)
     k_collide_mom_buf(Member m, const typename ST::T *__restrict__ src,
                       typename ST::T *__restrict__ dst,
                       const typename ST::R *__restrict__ mom) {
-    const int x = blockIdx.x * TP_BX + threadIdx.x;
-    const int y = blockIdx.y * TP_BY + threadIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
     if (x < m.nx && y < m.ny)
         collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, blockIdx.z);
@@ -350,6 +350,21 @@ static dim3 tp_grid(const Member &m) {
     return dim3((m.nx + TP_BX - 1) / TP_BX, (m.ny + TP_BY - 1) / TP_BY, m.nz);
 }
 
+// Blocks of the buffer-form moment passes (measured on 128^3): one 64-wide row
+// per block for the pull pass, 128 x 2 for the collision pass when rows are
+// long enough.
+static void mom_blocks(const Member &m, dim3 *gm, dim3 *bm, dim3 *gc, dim3 *bc) {
+    *bm = dim3(64, 1, 1);
+    *gm = dim3((m.nx + 63) / 64, m.ny, m.nz);
+    if (m.nx >= 128) {
+        *bc = dim3(128, 2, 1);
+        *gc = dim3((m.nx + 127) / 128, (m.ny + 1) / 2, m.nz);
+    } else {
+        *bc = dim3(TP_BX, TP_BY, 1);
+        *gc = tp_grid(m);
+    }
+}
+
 hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
                            void *dst, void *dens, hipStream_t st) {
     hipError_t err = hipErrorInvalidValue;
@@ -365,9 +380,11 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
             bool done = false;
             if constexpr (buf_form<D, ST>()) {
                 if (k.mom && !k.big) {
-                    hipLaunchKernelGGL((k_moments_buf<ST>), g, b, 0, st, m,
+                    dim3 gm, bm, gc, bc;
+                    mom_blocks(m, &gm, &bm, &gc, &bc);
+                    hipLaunchKernelGGL((k_moments_buf<ST>), gm, bm, 0, st, m,
                                        (const T *)src, (R *)dens);
-                    hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P>), g, b, 0, st, m,
+                    hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P>), gc, bc, 0, st, m,
                                        (const T *)src, (T *)dst, (const R *)dens);
                     done = true;
                 }
@@ -402,15 +419,16 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dn, NodeLaunch *sn,
             dn->func = k.mom ? (void *)&k_moments<D, ST> : (void *)&k_density<D, ST>;
             sn->func = k.mom ? (void *)&k_collide_mom<D, O, ST, P>
                              : (void *)&k_collide<D, O, ST, P>;
+            dn->grid = sn->grid = tp_grid(m);
+            dn->block = sn->block = dim3(TP_BX, TP_BY, 1);
+            dn->shmem = sn->shmem = 0;
             if constexpr (buf_form<D, ST>()) {
                 if (k.mom && !k.big) {
                     dn->func = (void *)&k_moments_buf<ST>;
                     sn->func = (void *)&k_collide_mom_buf<O, ST, P>;
+                    mom_blocks(m, &dn->grid, &dn->block, &sn->grid, &sn->block);
                 }
             }
-            dn->grid = sn->grid = tp_grid(m);
-            dn->block = sn->block = dim3(TP_BX, TP_BY, 1);
-            dn->shmem = sn->shmem = 0;
             ok = true;
         });
     });
