@@ -25,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,21 +39,22 @@ KERNELS = {"auto": 0, "two_pass": 1, "fused": 2, "fused_repull": 3, "fused_pipe"
            "fused_mom": 5, "fused_mom_pipe": 6, "two_pass_mom": 7}
 KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 OBS_EVERY = 2048
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "fused_e6_f32_128cube_traffic.txt")
-TRACE_MD = os.path.join(ROOT, "profiles", "fused_e6_f32_128cube_kernel_trace.md")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "step_e6_f32_128cube_traffic.txt")
+TRACE_MD = os.path.join(ROOT, "profiles", "step_e6_f32_128cube_kernel_trace.md")
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace "
-             "-o trace -- python3 bench.py --steps 300 --warmup 20 --cpu-steps 0 --variant-steps 0 --init tanh --kernel fused --tile 128 4 16",
+             "-o trace -- python3 bench.py --steps 300 --warmup 20 --cpu-steps 0 --variant-steps 0 --init tanh --kernel two_pass_mom",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch "
-             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh --kernel fused --tile 128 4 16",
+             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh --kernel two_pass_mom",
     "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write "
-             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh --kernel fused --tile 128 4 16",
+             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh --kernel two_pass_mom",
     "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_copy_fetch "
                   "-o cfetch -- python3 bench.py --copy-calib 1024",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_copy_write "
                   "-o cwrite -- python3 bench.py --copy-calib 1024",
 }
-KERNEL_SOURCES = ["paper_2112_02574_amd/csrc/fused_impl.h",
+KERNEL_SOURCES = ["paper_2112_02574_amd/csrc/step_kernels.hip",
+                  "paper_2112_02574_amd/csrc/fused_impl.h",
                   "paper_2112_02574_amd/csrc/fused_inst.hip",
                   "paper_2112_02574_amd/csrc/fused_kernels.hip",
                   "paper_2112_02574_amd/csrc/site_ops.h",
@@ -86,9 +88,14 @@ def _finite(v):
     return v if isinstance(v, (int, float)) and v == v and abs(v) != float("inf") else None
 
 
+STEP_KERNEL = re.compile(r"scmc::kb?_(fused|density|collide|moments|collide_mom)(_buf)?<")
+
+
 def summarize_profiles(outdir, L=128):
     """Write the profiles/ summaries from the rocprofv3 CSV output of the
-    commands in PROFILE_COMMANDS (run from the repository root)."""
+    commands in PROFILE_COMMANDS (run from the repository root).  A step is
+    one launch of each step kernel (one for the fused designs, two for the
+    two-pass ones); durations and counters are summed over them."""
     import csv
 
     def rows(sub, suffix):
@@ -102,19 +109,25 @@ def summarize_profiles(outdir, L=128):
         return sum(v) / len(v), len(v)
 
     stats = rows("prof_trace", "_kernel_stats.csv")
-    top = stats[0]["Name"]
-    prefix = top.split("(")[0]
-    fetch, nf = mean_counter("prof_fetch", prefix)
-    write, nw = mean_counter("prof_write", prefix)
+    step_rows = [r for r in stats if STEP_KERNEL.search(r["Name"])
+                 and "density64" not in r["Name"]]
+    names = [r["Name"].split("(")[0] for r in step_rows]
+    step_us = sum(float(r["AverageNs"]) for r in step_rows) / 1e3
+    fetch = write = 0.0
+    nf = nw = 0
+    for nm in names:
+        f, a = mean_counter("prof_fetch", nm)
+        w, b = mean_counter("prof_write", nm)
+        fetch, write, nf, nw = fetch + f, write + w, nf + a, nw + b
     cf, _ = mean_counter("prof_copy_fetch", "__amd_rocclr_copyBuffer")
     cw, _ = mean_counter("prof_copy_write", "__amd_rocclr_copyBuffer")
     copy_bytes = 1024 * (1 << 20)
     sf, sw = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
     N = L ** 3
     hbm = fetch * 1024 * sf + write * 1024 * sw
-    traffic = {"kernel": top, "sites": N, "dispatches": {"fetch": nf, "write": nw},
-               "fetch_size_kib_per_dispatch": round(fetch, 1),
-               "write_size_kib_per_dispatch": round(write, 1),
+    traffic = {"kernels": names, "sites": N, "dispatches": {"fetch": nf, "write": nw},
+               "fetch_size_kib_per_step": round(fetch, 1),
+               "write_size_kib_per_step": round(write, 1),
                "copy_calibration": {"bytes": copy_bytes, "fetch_size_kib": round(cf, 1),
                                     "write_size_kib": round(cw, 1), "fetch_scale": round(sf, 4),
                                     "write_scale": round(sw, 4)},
@@ -132,12 +145,13 @@ def summarize_profiles(outdir, L=128):
         lines.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f |" % (
             r["Name"].split("(")[0], r["Calls"], float(r["AverageNs"]) / 1e3,
             float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
-    avg_us = float(stats[0]["AverageNs"]) / 1e3
-    lines += ["", "Dominant kernel: %.1f us per step = %.0f MLUPS; algorithmic %d B/site -> %.0f GB/s "
-              "(%.1f%% of 8 TB/s)." % (avg_us, N / avg_us, 304, 304 * N / avg_us / 1e3,
-                                       304 * N / avg_us / 1e3 / 80),
-              "", "HBM traffic (rocprofv3 counters, scaled by a 1 GiB copy): FETCH_SIZE %.0f KiB x %.3f "
-              "+ WRITE_SIZE %.0f KiB x %.3f = %.1f MB per launch, %.3f x the algorithmic %.1f MB." % (
+    lines += ["", "Step kernels: %s." % ", ".join("`%s`" % n for n in names),
+              "", "One step: %.1f us = %.0f MLUPS; algorithmic %d B/site -> %.0f GB/s "
+              "(%.1f%% of 8 TB/s)." % (step_us, N / step_us, 304, 304 * N / step_us / 1e3,
+                                       304 * N / step_us / 1e3 / 80),
+              "", "HBM traffic per step (rocprofv3 counters summed over the step kernels, scaled by a "
+              "1 GiB copy): FETCH_SIZE %.0f KiB x %.3f + WRITE_SIZE %.0f KiB x %.3f = %.1f MB, "
+              "%.3f x the algorithmic %.1f MB." % (
                   fetch, sf, write, sw, hbm / 1e6, hbm / (304 * N), 304 * N / 1e6), ""]
     with open(TRACE_MD, "w") as fh:
         fh.write("\n".join(lines))
@@ -322,7 +336,8 @@ def run(args):
 def precision_study(args, out_md):
     """256^3 D3Q19 / E6 B-rich droplet, R0 = 64, g_AB = 1.8, g_AA = -0.2, psi = n:
     the same run with populations stored in FP64, FP32, FP16 offsets and BF16
-    offsets (FP32 arithmetic for the last three), observables every 2^11 steps.
+    offsets (FP32 arithmetic for the last four; offsets rounded to nearest
+    even, or stochastically), observables every 2^11 steps.
     FP64 storage stands in for the oracle at this size (its parity with the
     oracle is tested on smaller lattices); errors are stated against it."""
     import torch
@@ -339,10 +354,15 @@ def precision_study(args, out_md):
     init = inputs.droplet(L, L, L, R=R0, a_rich=False, bulk=bulk)
     n0 = (0.5 * (bulk[0] + bulk[2]), 0.5 * (bulk[1] + bulk[3]))
     runs = {}
-    for name, storage in (("f64", scmc.F64), ("f32", scmc.F32), ("f16_offset", scmc.F16_OFF),
-                          ("bf16_offset", scmc.BF16_OFF)):
+    for name, storage, rounding in (
+            ("f64", scmc.F64, 0), ("f32", scmc.F32, 0),
+            ("f16_offset", scmc.F16_OFF, scmc.ROUND_NEAREST),
+            ("bf16_offset", scmc.BF16_OFF, scmc.ROUND_NEAREST),
+            ("f16_offset_sr", scmc.F16_OFF, scmc.ROUND_STOCHASTIC),
+            ("bf16_offset_sr", scmc.BF16_OFF, scmc.ROUND_STOCHASTIC)):
         sim = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), g=G_ASYM, storage=storage,
-                                    n0=n0), device=dev, stream=stream)
+                                    n0=n0, rounding=rounding, seed=12345),
+                       device=dev, stream=stream)
         if storage != scmc.F64:
             sim.scmc_autotune(args.tune_cache)
         sim.scmc_set_density(*init)
@@ -371,7 +391,8 @@ def precision_study(args, out_md):
              "g_AB = 1.8, g_AA = -0.2, g_BB = 0, psi = n; n0 = %s (midpoints of the bulk values). "
              "%d steps per run, observables every 2^11 steps. FP64 storage is the reference "
              "(its parity with the oracle is tested on smaller lattices)." % (
-                 [round(v, 9) for v in bulk], [round(v, 6) for v in n0], args.steps), "",
+                 [round(float(v), 9) for v in bulk], [round(float(v), 6) for v in n0],
+                 args.steps), "",
              "Command (repository root, one MI355X):", "",
              "    python bench.py --precision profiles/precision_256cube_asym.md --size %d --steps %d"
              % (L, args.steps), "",

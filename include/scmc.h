@@ -95,6 +95,14 @@ typedef enum {
                                      without pulling again (every lattice,
                                      stencil and storage) */
 } scmc_kernel;
+typedef enum {
+    SCMC_ROUND_NEAREST = 0,   /* FP16 / BF16 offsets rounded to nearest even */
+    SCMC_ROUND_STOCHASTIC = 1 /* rounded up with probability equal to the
+                                 discarded fraction of an ulp (unbiased);
+                                 the random bits come from a counter-based
+                                 hash of (seed, step, site, J, i), so runs
+                                 are reproducible.  Two-pass designs only. */
+} scmc_rounding;
 typedef enum { SCMC_OBS_FLAT = 0, SCMC_OBS_DROPLET = 1 } scmc_obs_kind;
 
 typedef struct {
@@ -110,6 +118,8 @@ typedef struct {
     double n0[2];     /* offset references of the FP16/BF16 storage */
     int kernel;       /* scmc_kernel */
     int tile[3];      /* fused-kernel tile (x, y, z-chunk); 0 = default */
+    int rounding;     /* scmc_rounding of FP16 / BF16 offset stores */
+    unsigned int seed; /* seed of the stochastic rounding */
 } scmc_problem;
 
 typedef struct {

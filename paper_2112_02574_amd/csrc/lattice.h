@@ -138,6 +138,7 @@ struct StoreF64 {
     __device__ __forceinline__ static void store(T *p, long i, R v, R) {
         __builtin_nontemporal_store(v, p + i);
     }
+    __device__ __forceinline__ static T to_raw_sr(R v, R, unsigned) { return v; }
 };
 
 struct StoreF32 {
@@ -150,6 +151,7 @@ struct StoreF32 {
     __device__ __forceinline__ static void store(T *p, long i, R v, R) {
         __builtin_nontemporal_store(v, p + i);
     }
+    __device__ __forceinline__ static T to_raw_sr(R v, R, unsigned) { return v; }
 };
 
 struct StoreF16 {
@@ -168,6 +170,15 @@ struct StoreF16 {
     __device__ __forceinline__ static void store(T *p, long i, R v, R ref) {
         const T h = __half_as_ushort(__float2half_rn(v - ref));
         __builtin_nontemporal_store(h, p + i);
+    }
+    // Stochastic rounding: 13 random bits added below the half's last
+    // mantissa bit, then truncation.  Half subnormals (|h| < 2^-14) are
+    // rounded to nearest, their absolute error being below 2^-25.
+    __device__ __forceinline__ static T to_raw_sr(R v, R ref, unsigned r) {
+        const float x = v - ref;
+        if (!(fabsf(x) >= 6.103515625e-05f) || fabsf(x) > 6.5e4f) return to_raw(v, ref);
+        const unsigned u = __float_as_uint(x) + (r & 0x1FFFu);
+        return __half_as_ushort(__float2half_rz(__uint_as_float(u)));
     }
 };
 
@@ -204,6 +215,15 @@ struct StoreBF16 {
     __device__ __forceinline__ static void store(T *p, long i, R v, R ref) {
         const T h = f32_to_bf16_rne(v - ref);
         __builtin_nontemporal_store(h, p + i);
+    }
+    // Stochastic rounding: 16 random bits added below the kept half of the
+    // binary32 pattern, then truncation (sign-magnitude: unbiased for both
+    // signs); infinities and NaN go the nearest-even way.
+    __device__ __forceinline__ static T to_raw_sr(R v, R ref, unsigned r) {
+        const float x = v - ref;
+        const uint32_t u = __float_as_uint(x);
+        if ((u & 0x7f800000u) == 0x7f800000u) return f32_to_bf16_rne(x);
+        return (uint16_t)((u + (r & 0xFFFFu)) >> 16);
     }
 };
 

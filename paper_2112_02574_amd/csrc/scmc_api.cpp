@@ -158,6 +158,8 @@ struct Common {
     double *vel64 = nullptr;
     double *partials = nullptr;
     double *small = nullptr;  // stats / line / flat outputs
+    unsigned *ctr = nullptr;  // step counter of the stochastic rounding
+    unsigned ctr_host = 0;
     int nblocks = 0;
     int cur = 0;
     int64_t step = 0;
@@ -250,6 +252,15 @@ int validate(const scmc_problem *p, std::string *why) {
     if (p->g[0][1] != p->g[1][0]) return bad(SCMC_EINVAL, "g_AB != g_BA");
     if (!std::isfinite(p->n0[0]) || !std::isfinite(p->n0[1]))
         return bad(SCMC_EINVAL, "non-finite n0");
+    if (p->rounding != SCMC_ROUND_NEAREST && p->rounding != SCMC_ROUND_STOCHASTIC)
+        return bad(SCMC_EINVAL, "unknown rounding");
+    if (p->rounding == SCMC_ROUND_STOCHASTIC) {
+        if (p->storage != SCMC_F16_OFF && p->storage != SCMC_BF16_OFF)
+            return bad(SCMC_EINVAL, "stochastic rounding needs FP16 / BF16 offset storage");
+        if (p->kernel != SCMC_KERNEL_AUTO && p->kernel != SCMC_KERNEL_TWO_PASS &&
+            p->kernel != SCMC_KERNEL_TWO_PASS_MOM)
+            return bad(SCMC_EUNSUPPORTED, "stochastic rounding runs in the two-pass designs");
+    }
     return SCMC_OK;
 }
 
@@ -289,6 +300,9 @@ Member member_of(const scmc_problem &p) {
     m.n0[1] = p.n0[1];
     m.psi_self = p.psi_self;
     m.self_on = (p.g[0][0] != 0.0 ? 1 : 0) | (p.g[1][1] != 0.0 ? 2 : 0);
+    m.sr = p.rounding == SCMC_ROUND_STOCHASTIC;
+    m.seed = p.seed;
+    m.step_ctr = nullptr;  // bound to the workspace's counter by the handle
     return m;
 }
 
@@ -299,7 +313,8 @@ int choose_kernel(const scmc_problem &p, const StepKey &k, int *kernel,
     // at tau = 1 the default is the moment two-pass design (the fastest
     // untuned choice on a 128^3 sweep); the autotuner may pick a fused one
     if (p.kernel == SCMC_KERNEL_TWO_PASS || p.kernel == SCMC_KERNEL_TWO_PASS_MOM ||
-        (p.kernel == SCMC_KERNEL_AUTO && k.mom && t[0] == 0)) {
+        (p.kernel == SCMC_KERNEL_AUTO && k.mom && t[0] == 0) ||
+        (p.kernel == SCMC_KERNEL_AUTO && p.rounding == SCMC_ROUND_STOCHASTIC)) {
         *kernel = SCMC_KERNEL_TWO_PASS;
         tile[0] = tile[1] = tile[2] = 0;
         return SCMC_OK;
@@ -331,7 +346,7 @@ int public_kernel(int kernel, int variant, int mom) {
 }
 
 struct Plan {
-    size_t pop, dens, dens64, vel64, partials, small, members, tiles, total;
+    size_t pop, dens, dens64, vel64, partials, small, ctr, members, tiles, total;
 };
 
 Plan plan_of(const std::vector<scmc_problem> &ps, int ntiles) {
@@ -353,10 +368,11 @@ Plan plan_of(const std::vector<scmc_problem> &ps, int ntiles) {
     pl.vel64 = align_up(3 * nmax * 8);
     pl.partials = align_up((size_t)nb * 9 * 8);
     pl.small = align_up((3 * (nxmax / 2 + 1) + 3 + 2 * nxmax + 1 + 16) * 8);
+    pl.ctr = align_up(sizeof(unsigned));
     pl.members = ps.size() > 1 ? align_up(ps.size() * sizeof(Member)) : 0;
     pl.tiles = ntiles > 0 ? align_up((size_t)ntiles * sizeof(Tile)) : 0;
     pl.total = 2 * pl.pop + pl.dens + pl.dens64 + pl.vel64 + pl.partials +
-               pl.small + pl.members + pl.tiles;
+               pl.small + pl.ctr + pl.members + pl.tiles;
     return pl;
 }
 
@@ -376,6 +392,8 @@ void bind(Common &c, const Plan &pl, char *ws, int nblocks) {
     p += pl.partials;
     c.small = (double *)p;
     p += pl.small;
+    c.ctr = (unsigned *)p;
+    p += pl.ctr;
     c.nblocks = nblocks;
 }
 
@@ -417,6 +435,15 @@ int upload_state(Common &c, const Lat &L, const double *f, void *dst_dev) {
                 }
         }
     HIPCHK(c, hipMemcpyAsync(dst_dev, host.data(), host.size(),
+                             hipMemcpyHostToDevice, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    return SCMC_OK;
+}
+
+// Counter seeding the stochastic rounding: the number of steps taken.
+int set_step_counter(Common &c, int64_t step) {
+    c.ctr_host = (unsigned)step;
+    HIPCHK(c, hipMemcpyAsync(c.ctr, &c.ctr_host, sizeof(unsigned),
                              hipMemcpyHostToDevice, c.stream));
     HIPCHK(c, hipStreamSynchronize(c.stream));
     return SCMC_OK;
@@ -820,6 +847,7 @@ int scmc_create(const scmc_problem *p, void *d_ws, size_t ws_bytes,
     c.ws = (char *)d_ws;
     c.ws_bytes = ws_bytes;
     bind(c, pl, c.ws, stats_blocks(s->lat.m));
+    s->lat.m.step_ctr = c.ctr;
     *out = s;
     return SCMC_OK;
 }
@@ -834,6 +862,7 @@ int scmc_destroy(scmc_sim *s) {
 int scmc_set_density(scmc_sim *s, const double *nA, const double *nB) {
     if (!s || !nA || !nB) return SCMC_EINVAL;
     int rc = set_density_impl(s->c, s->lat, nA, nB, s->c.pop[0]);
+    if (!rc) rc = set_step_counter(s->c, 0);
     if (rc) return rc;
     s->c.cur = 0;
     s->c.step = 0;
@@ -848,6 +877,7 @@ int scmc_set_populations(scmc_sim *s, const double *f, int64_t step) {
         if (!std::isfinite(f[i]))
             return fail(s->c, SCMC_EINVAL, "non-finite population %zu", i);
     int rc = upload_state(s->c, s->lat, f, s->c.pop[0]);
+    if (!rc) rc = set_step_counter(s->c, step);
     if (rc) return rc;
     s->c.cur = 0;
     s->c.step = step;
@@ -1045,6 +1075,7 @@ static int batch_check(const scmc_problem *ps, int count, std::string *why) {
         if (ps[i].lattice != ps[0].lattice || ps[i].stencil != ps[0].stencil ||
             ps[i].storage != ps[0].storage || ps[i].tau[0] != ps[0].tau[0] ||
             ps[i].psi_self != ps[0].psi_self || ps[i].kernel != ps[0].kernel ||
+            ps[i].rounding != ps[0].rounding ||
             ps[i].tile[0] != ps[0].tile[0] || ps[i].tile[1] != ps[0].tile[1] ||
             ps[i].tile[2] != ps[0].tile[2])
             return SCMC_EINVAL;
@@ -1101,7 +1132,7 @@ int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
     int nbmax = 0;
     for (auto &p : v) nbmax = std::max(nbmax, stats_blocks(member_of(p)));
     bind(c, pl, c.ws, nbmax);
-    char *tail = (char *)c.small + pl.small;
+    char *tail = (char *)c.ctr + pl.ctr;
     b->d_members = (Member *)tail;
     tail += align_up(count * sizeof(Member));
     b->d_tiles = (Tile *)tail;
@@ -1116,6 +1147,7 @@ int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
         L.dim = lattice_dim(v[i].lattice);
         L.m.pop_off = pop_off;
         L.m.dens_off = dens_off;
+        L.m.step_ctr = c.ctr;
         const size_t N = (size_t)L.m.N;
         pop_off += (long long)(align_up(2 * L.q * N * storage_bytes(v[i].storage)) /
                                storage_bytes(v[i].storage));
@@ -1169,6 +1201,7 @@ int scmc_batch_set_density(scmc_batch *b, int i, const double *nA,
         return fail(c, SCMC_ESTATE, "members are set before the first step");
     int rc = set_density_impl(c, b->lats[i], nA, nB,
                               (void *)member_pop(b, i, 0));
+    if (!rc) rc = set_step_counter(c, 0);
     if (rc) return rc;
     b->member_set[i] = true;
     c.initialized = std::all_of(b->member_set.begin(), b->member_set.end(),
@@ -1258,6 +1291,11 @@ std::vector<Candidate> candidates(const scmc_problem &p, const StepKey &k0, int 
         variants = {k0.repull};
     }
     std::vector<Candidate> out;
+    if (p.rounding == SCMC_ROUND_STOCHASTIC) {  // two-pass designs only
+        if (p.kernel == SCMC_KERNEL_AUTO && tau1)
+            out.push_back(Candidate{SCMC_KERNEL_TWO_PASS, 0, 1, {0, 0, 0}});
+        return out;
+    }
     for (int variant : variants)
         for (const auto &t : tiles) {
             if (t[0] > 2 * nx) continue;  // mostly idle lanes
@@ -1274,10 +1312,33 @@ std::vector<Candidate> candidates(const scmc_problem &p, const StepKey &k0, int 
 }
 
 std::string cache_key(const scmc_problem &p, int count) {
-    char buf[160];
-    snprintf(buf, sizeof buf, "lattice=%d stencil=%d storage=%d psi=%d box=%dx%dx%d members=%d",
-             p.lattice, p.stencil, p.storage, p.psi_self, p.nx, p.ny, p.nz, count);
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "lattice=%d stencil=%d storage=%d psi=%d rounding=%d tau1=%d kernel=%d "
+             "box=%dx%dx%d members=%d",
+             p.lattice, p.stencil, p.storage, p.psi_self, p.rounding, p.tau[0] == 1.0 ? 1 : 0,
+             p.kernel, p.nx, p.ny, p.nz, count);
     return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, Candidate *c);
+
+bool same(const Candidate &a, const Candidate &b) {
+    return a.kernel == b.kernel && a.variant == b.variant && a.mom == b.mom &&
+           a.tile[0] == b.tile[0] && a.tile[1] == b.tile[1] && a.tile[2] == b.tile[2];
+}
+
+// a cached choice is used only if this problem can still run it
+bool cached_choice(const char *path, const std::string &key,
+                   const std::vector<Candidate> &cands, Candidate *c) {
+    Candidate t;
+    if (!cache_lookup(path, key, &t)) return false;
+    for (const Candidate &x : cands)
+        if (same(x, t)) {
+            *c = t;
+            return true;
+        }
+    return false;
 }
 
 bool cache_lookup(const char *path, const std::string &key, Candidate *c) {
@@ -1355,7 +1416,7 @@ int scmc_autotune(scmc_sim *s, const char *cache_path, int *tile) {
         return fail(c, SCMC_EUNSUPPORTED, "no fused kernel for this problem");
     const std::string key = cache_key(p, 1);
     Candidate best{};
-    if (!cache_lookup(cache_path, key, &best)) {
+    if (!cached_choice(cache_path, key, cands, &best)) {
         // scratch state: a uniform mixture at rest
         std::vector<double> nA(s->lat.m.N, 0.5), nB(s->lat.m.N, 0.5);
         int rc = set_density_impl(c, s->lat, nA.data(), nB.data(), c.pop[0]);
@@ -1412,7 +1473,7 @@ int scmc_batch_autotune(scmc_batch *b, const char *cache_path, int *tile) {
         return SCMC_OK;
     };
     Candidate best{};
-    if (!cache_lookup(cache_path, key, &best)) {
+    if (!cached_choice(cache_path, key, cands, &best)) {
         for (int i = 0; i < (int)b->lats.size(); ++i) {
             std::vector<double> nA(b->lats[i].m.N, 0.5), nB(b->lats[i].m.N, 0.5);
             int rc = set_density_impl(c, b->lats[i], nA.data(), nB.data(),

@@ -21,6 +21,10 @@ struct Member {
     double n0[2];     // offset references (FP16 / BF16 storage)
     int psi_self;     // 0: psi = n, 1: psi = exp(-1/n)
     int self_on;      // bit J set when g_JJ != 0
+    int sr;           // 1: stochastic rounding of FP16 / BF16 stores
+    unsigned seed;    // its seed
+    unsigned *step_ctr;  // device step counter: advanced by the first pass of
+                         // a two-pass step, read by the second (random stream)
 };
 
 // A unit of work of the batched launches: member index and tile origin.

@@ -20,6 +20,29 @@ __device__ __forceinline__ int wrap1(int v, int n) {
     return v < 0 ? v + n : (v >= n ? v - n : v);
 }
 
+// 32-bit integer hash (xor-shift-multiply finaliser, constants from
+// C. Wellons' "lowbias32") used to seed the stochastic-rounding stream.
+__host__ __device__ __forceinline__ unsigned hash32(unsigned x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Random stream of one site and step: a hashed key, then a linear
+// congruential step per stored value (its top 16 bits are used).
+struct SiteRng {
+    unsigned s;
+    __device__ __forceinline__ SiteRng(unsigned seed, unsigned step, unsigned site)
+        : s(hash32(seed ^ hash32(step * 0x9E3779B9u ^ hash32(site)))) {}
+    __device__ __forceinline__ unsigned next() {
+        s = s * 1664525u + 1013904223u;
+        return s >> 16;
+    }
+};
+
 template <class R, int PSI> __device__ __forceinline__ R psi_of(R n) {
     if constexpr (PSI == 0) {
         return n;
@@ -248,9 +271,23 @@ __device__ __forceinline__ void site_collide_store(
     const typename ST::R (&FB)[3], typename ST::T *__restrict__ dst, long s) {
     using R = typename ST::R;
     typename ST::T *base = dst + m.pop_off;
+    if (m.sr) {
+        SiteRng rng(m.seed, *m.step_ctr, (unsigned)(m.pop_off + s));
+        site_collide<D, R>(m, f, nA, nB, FA, FB, [&](int J, int i, R v, R ref) {
+            __builtin_nontemporal_store(ST::to_raw_sr(v, ref, rng.next()),
+                                        base + (long)(J * Lattice<D>::Q + i) * m.N + s);
+        });
+        return;
+    }
     site_collide<D, R>(m, f, nA, nB, FA, FB, [&](int J, int i, R v, R ref) {
         ST::store(base, (long)(J * Lattice<D>::Q + i) * m.N + s, v, ref);
     });
+}
+
+// The first pass of a two-pass step advances the step counter that seeds the
+// second pass's stochastic rounding (one thread of the launch).
+__device__ __forceinline__ void advance_step_counter(const Member &m, bool first) {
+    if (m.sr && first && threadIdx.x == 0 && threadIdx.y == 0) m.step_ctr[0] += 1u;
 }
 
 // ---- raw-buffer access with 32-bit offsets (used by the fused kernels) ----

@@ -29,6 +29,7 @@ __global__ void __launch_bounds__(256)
     k_density(Member m, const typename ST::T *__restrict__ src,
               typename ST::R *__restrict__ dens) {
     using R = typename ST::R;
+    advance_step_counter(m, blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
     const int x = blockIdx.x * TP_BX + threadIdx.x;
     const int y = blockIdx.y * TP_BY + threadIdx.y;
     const int z = blockIdx.z;
@@ -108,6 +109,14 @@ __device__ __forceinline__ void collide_mom_site(const Member &m,
                                         b = q.y;
                                     });
     typename ST::T *out = dst + m.pop_off;
+    if (m.sr) {
+        SiteRng rng(m.seed, *m.step_ctr, (unsigned)(m.pop_off + s));
+        collide_tau1<D, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
+            __builtin_nontemporal_store(ST::to_raw_sr(v, ref, rng.next()),
+                                        out + (long)(J * Lattice<D>::Q + i) * m.N + s);
+        });
+        return;
+    }
     collide_tau1<D, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
         ST::store(out, (long)(J * Lattice<D>::Q + i) * m.N + s, v, ref);
     });
@@ -151,6 +160,14 @@ __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopB
                                         b = q.y;
                                     });
     const int voff = s * (int)sizeof(T);
+    if (m.sr) {
+        SiteRng rng(m.seed, *m.step_ctr, (unsigned)(m.pop_off + s));
+        collide_tau1<3, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
+            RawBuf<T>::store_nt(ST::to_raw_sr(v, ref, rng.next()), db.r[J], voff,
+                                i * db.plane_bytes);
+        });
+        return;
+    }
     collide_tau1<3, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
         RawBuf<T>::store_nt(ST::to_raw(v, ref), db.r[J], voff, i * db.plane_bytes);
     });
@@ -160,6 +177,7 @@ template <class ST>
 __global__ void __launch_bounds__(256)
     k_moments_buf(Member m, const typename ST::T *__restrict__ src,
                   typename ST::R *__restrict__ mom) {
+    advance_step_counter(m, blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
@@ -186,6 +204,7 @@ __global__ void __launch_bounds__(256)
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tiles[t];
         const Member m = members[tl.member];
+        advance_step_counter(m, t == 0);
         const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
         const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y;
         if (x < m.nx && y < m.ny) moments_site_buf<ST>(m, sb, mom, x, y, tl.z0);
@@ -212,6 +231,7 @@ template <int D, class ST>
 __global__ void __launch_bounds__(256)
     k_moments(Member m, const typename ST::T *__restrict__ src,
               typename ST::R *__restrict__ mom) {
+    advance_step_counter(m, blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
     const int x = blockIdx.x * TP_BX + threadIdx.x;
     const int y = blockIdx.y * TP_BY + threadIdx.y;
     if (x < m.nx && y < m.ny) moments_site<D, ST>(m, src, mom, x, y, blockIdx.z);
@@ -236,6 +256,7 @@ __global__ void __launch_bounds__(256)
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tiles[t];
         const Member m = members[tl.member];
+        advance_step_counter(m, t == 0);
         const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y;
         if (x < m.nx && y < m.ny) moments_site<D, ST>(m, src, mom, x, y, tl.z0);
     }
@@ -268,6 +289,7 @@ __global__ void __launch_bounds__(256)
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tiles[t];
         const Member m = members[tl.member];
+        advance_step_counter(m, t == 0);
         const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y, z = tl.z0;
         if (x < m.nx && y < m.ny) {
             R f[2][Lattice<D>::Q];

@@ -22,6 +22,7 @@ PSI_N, PSI_EXP_NEG_INV = 0, 1
 F64, F32, F16_OFF, BF16_OFF = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_TWO_PASS, KERNEL_FUSED, KERNEL_FUSED_REPULL, KERNEL_FUSED_PIPE = 0, 1, 2, 3, 4
 KERNEL_FUSED_MOM, KERNEL_FUSED_MOM_PIPE, KERNEL_TWO_PASS_MOM = 5, 6, 7
+ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
 OBS_FLAT, OBS_DROPLET = 0, 1
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16_OFF: "f16", BF16_OFF: "bf16"}
 
@@ -42,7 +43,8 @@ class Problem(ctypes.Structure):
                 ("tau", ctypes.c_double * 2), ("g", (ctypes.c_double * 2) * 2),
                 ("psi_self", ctypes.c_int), ("storage", ctypes.c_int),
                 ("n0", ctypes.c_double * 2), ("kernel", ctypes.c_int),
-                ("tile", ctypes.c_int * 3)]
+                ("tile", ctypes.c_int * 3), ("rounding", ctypes.c_int),
+                ("seed", ctypes.c_uint)]
 
 
 class Stats(ctypes.Structure):
@@ -145,7 +147,7 @@ def _f64(a, n):
 
 def problem(lattice=D3Q19, stencil=E6, shape=(64, 64, 64), tau=1.0,
             g=((0.0, 1.8), (1.8, 0.0)), psi_self=PSI_N, storage=F32, n0=(0.52, 0.52),
-            kernel=KERNEL_AUTO, tile=(0, 0, 0)):
+            kernel=KERNEL_AUTO, tile=(0, 0, 0), rounding=0, seed=0):
     """Problem struct; shape is (nz, ny, nx) in 3D or (ny, nx) in 2D."""
     p = Problem()
     lib().scmc_problem_init(ctypes.byref(p))
@@ -165,6 +167,8 @@ def problem(lattice=D3Q19, stencil=E6, shape=(64, 64, 64), tau=1.0,
     p.kernel = kernel
     for a in range(3):
         p.tile[a] = int(tile[a])
+    p.rounding = int(rounding)
+    p.seed = int(seed) & 0xFFFFFFFF
     return p
 
 

@@ -67,6 +67,10 @@ def test_workspace_planner():
     (lambda p: setattr(p, "storage", 9), -1),
     (lambda p: setattr(p, "psi_self", 3), -1),
     (lambda p: setattr(p, "kernel", 8), -1),
+    (lambda p: setattr(p, "rounding", 2), -1),
+    (lambda p: setattr(p, "rounding", scmc.ROUND_STOCHASTIC), -1),   # FP32 storage
+    (lambda p: (setattr(p, "rounding", scmc.ROUND_STOCHASTIC), setattr(p, "storage", scmc.BF16_OFF),
+                setattr(p, "kernel", scmc.KERNEL_FUSED)), -2),      # two-pass designs only
     (lambda p: (setattr(p, "kernel", scmc.KERNEL_FUSED_MOM), p.tau.__setitem__(0, 0.8),
                 p.tau.__setitem__(1, 0.8)), -2),          # moment ring needs tau = 1
 ])

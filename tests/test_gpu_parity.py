@@ -393,3 +393,62 @@ def test_flat_equilibrium_matches_oracle(lattice, stencil, gaa, lx):
         assert err < 1e-12, err
     else:
         assert abs(steps - wsteps) == 2048 and err < 1e-10, (steps, wsteps, err)
+
+
+@pytest.mark.parametrize("storage,mant", [(scmc.BF16_OFF, 8), (scmc.F16_OFF, 11)])
+def test_stochastic_rounding_single_step(storage, mant):
+    """One step with stochastic rounding of the FP16 / BF16 offsets against
+    the same step in FP32 from the same (decoded) state: every stored value is
+    one of the two neighbours of the exact one, the rounding is unbiased on
+    average (where nearest-even rounding keeps a half-ulp spread), and the
+    stream is reproducible for a seed and differs between seeds."""
+    shape = (20, 24, 32)
+    nA, nB = inputs.droplet(32, 24, 20, R=6.0)
+    g = ((-0.2, 1.8), (1.8, 0.0))
+
+    def run(seed, rounding=scmc.ROUND_STOCHASTIC):
+        s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, shape, g=g, storage=storage,
+                                  rounding=rounding, seed=seed))
+        s.scmc_set_density(nA, nB)
+        f0, _ = s.scmc_get_populations()
+        s.scmc_step(1)
+        f1, _ = s.scmc_get_populations()
+        s.close()
+        return f0, f1
+
+    f0, f1 = run(7)
+    _, f1b = run(7)
+    _, f1c = run(8)
+    _, f1n = run(7, scmc.ROUND_NEAREST)
+    assert np.array_equal(f1, f1b)
+    assert not np.array_equal(f1, f1c)
+    ref = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, shape, g=g, storage=scmc.F32))
+    ref.scmc_set_populations(f0, 0)
+    ref.scmc_step(1)
+    fr, _ = ref.scmc_get_populations()
+    xi, w = scmc.velocities(scmc.D3Q19)
+    h = np.abs(fr - (np.array(w)[None, :, None, None, None] * 0.52))  # |offset|, n0 = 0.52
+    ulp = 2.0 ** (np.floor(np.log2(np.maximum(h, 1e-30))) - (mant - 1))
+    big = h > 1e-3   # normal range of both formats, away from zero offsets
+    e_sr = ((f1 - fr) / ulp)[big]
+    e_rn = ((f1n - fr) / ulp)[big]
+    assert np.abs(e_sr).max() <= 1.0 + 1e-3
+    assert np.abs(e_rn).max() <= 0.5 + 1e-3
+    assert abs(e_sr.mean()) < 0.01
+    # really rounds up and down, not to nearest: for a fraction f of an ulp the
+    # expected |error| is 2 f (1 - f) >= min(f, 1 - f), the nearest-even error
+    assert np.abs(e_sr).mean() > np.abs(e_rn).mean()
+    assert (f1 != f1n).mean() > 0.05
+
+
+def test_autotune_cache_respects_rounding(tmp_path):
+    """A cached choice made for nearest-even rounding (possibly a fused
+    design) is not reused for stochastic rounding, which runs two-pass only."""
+    cache = str(tmp_path / "tune.txt")
+    shape = (24, 32, 40)
+    s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, shape, storage=scmc.BF16_OFF))
+    s.scmc_autotune(cache)
+    s2 = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, shape, storage=scmc.BF16_OFF,
+                               rounding=scmc.ROUND_STOCHASTIC, seed=3))
+    s2.scmc_autotune(cache)
+    assert s2.scmc_config()[0] == scmc.KERNEL_TWO_PASS_MOM
