@@ -180,8 +180,9 @@ __device__ __forceinline__ void site_collide(const Member &m,
         const R *F = J == 0 ? FA : FB;
         const R nJ = J == 0 ? nA : nB;
         const R uF = ux * F[0] + uy * F[1] + uz * F[2];
+        R moving = 0;
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
+        for (int i = 1; i < L::Q; ++i) {
             const R cx = (R)L::CX[i], cy = (R)L::CY[i], cz = (R)L::CZ[i];
             const R xu = cx * ux + cy * uy + cz * uz;
             const R xF = cx * F[0] + cy * F[1] + cz * F[2];
@@ -191,7 +192,12 @@ __device__ __forceinline__ void site_collide(const Member &m,
             const R S = w * (R(3) * xF + R(9) * xu * xF - R(3) * uF);
             const R out = f[J][i] - omega * (f[J][i] - feq) + cf * S;
             sink(J, i, out, w * n0[J]);
+            moving += out;
         }
+        // rest population from the mass balance sum_i f*_i = n_J (BGK and
+        // the Guo source conserve mass; rounded weights would not, by the
+        // same relative amount every step)
+        sink(J, 0, nJ - moving, (R)L::W[0] * n0[J]);
     }
 }
 
@@ -244,7 +250,7 @@ __device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[5],
         const R nJ = J == 0 ? nA : nB;
         const R uF = ux * F[0] + uy * F[1] + uz * F[2];
         const R a = nJ * (R(1) - R(1.5) * uu) - R(1.5) * uF;
-        sink(J, 0, (R)L::W[0] * a, (R)L::W[0] * n0[J]);
+        R moving = 0;
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
             const int ib = OP.opp[i];
@@ -259,7 +265,12 @@ __device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[5],
             const R O = w * (R(3) * t + R(1.5) * xF);
             sink(J, i, E + O, w * n0[J]);
             sink(J, ib, E - O, w * n0[J]);
+            moving += (E + O) + (E - O);
         }
+        // the rest population closes the mass balance sum_i f*_i = n_J, which
+        // the rounded weights (their binary sum is not exactly 1) would bias
+        // by the same relative amount every step
+        sink(J, 0, nJ - moving, (R)L::W[0] * n0[J]);
     }
 }
 
