@@ -1044,12 +1044,14 @@ static int batch_tiles(const std::vector<scmc_problem> &ps, int kernel,
     out->clear();
     for (int i = 0; i < (int)ps.size(); ++i) {
         const scmc_problem &p = ps[i];
-        const int tx = kernel == SCMC_KERNEL_FUSED ? tile[0] : 64;
-        const int ty = kernel == SCMC_KERNEL_FUSED ? tile[1] : 4;
-        const int tz = kernel == SCMC_KERNEL_FUSED ? tile[2] : 1;
-        for (int z = 0; z < p.nz; z += tz)
-            for (int y = 0; y < p.ny; y += ty)
-                for (int x = 0; x < p.nx; x += tx) out->push_back({i, x, y, z});
+        if (kernel != SCMC_KERNEL_FUSED) {  // runs of 256 consecutive sites
+            const int N = p.nx * p.ny * p.nz;
+            for (int s0 = 0; s0 < N; s0 += 256) out->push_back({i, s0, 0, 0});
+            continue;
+        }
+        for (int z = 0; z < p.nz; z += tile[2])
+            for (int y = 0; y < p.ny; y += tile[1])
+                for (int x = 0; x < p.nx; x += tile[0]) out->push_back({i, x, y, z});
     }
     return (int)out->size();
 }

@@ -24,6 +24,21 @@ namespace scmc {
 
 constexpr int TP_BX = 64, TP_BY = 4;  // two-pass block: 64 x 4 sites
 
+// Batched two-pass tiles are runs of TP_BX * TP_BY consecutive sites of one
+// member (x fastest, rows wrap), so lattices whose rows are not a multiple of
+// 64 leave no lanes idle.  Site of this thread in tile tl, false past the end.
+__device__ __forceinline__ bool tile_site(const Member &m, const Tile &tl, int &x, int &y,
+                                          int &z) {
+    const int s = tl.x0 + threadIdx.y * TP_BX + threadIdx.x;
+    if (s >= m.N) return false;
+    const int nxy = m.nx * m.ny;
+    z = s / nxy;
+    const int r = s - z * nxy;
+    y = r / m.nx;
+    x = r - y * m.nx;
+    return true;
+}
+
 template <int D, class ST>
 __global__ void __launch_bounds__(256)
     k_density(Member m, const typename ST::T *__restrict__ src,
@@ -206,8 +221,8 @@ __global__ void __launch_bounds__(256)
         const Member m = members[tl.member];
         advance_step_counter(m, t == 0);
         const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
-        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y;
-        if (x < m.nx && y < m.ny) moments_site_buf<ST>(m, sb, mom, x, y, tl.z0);
+        int x, y, z;
+        if (tile_site(m, tl, x, y, z)) moments_site_buf<ST>(m, sb, mom, x, y, z);
     }
 }
 
@@ -221,9 +236,8 @@ __global__ void __launch_bounds__(256)
         const Tile tl = tiles[t];
         const Member m = members[tl.member];
         const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
-        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y;
-        if (x < m.nx && y < m.ny)
-            collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, tl.z0);
+        int x, y, z;
+        if (tile_site(m, tl, x, y, z)) collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, z);
     }
 }
 
@@ -257,8 +271,8 @@ __global__ void __launch_bounds__(256)
         const Tile tl = tiles[t];
         const Member m = members[tl.member];
         advance_step_counter(m, t == 0);
-        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y;
-        if (x < m.nx && y < m.ny) moments_site<D, ST>(m, src, mom, x, y, tl.z0);
+        int x, y, z;
+        if (tile_site(m, tl, x, y, z)) moments_site<D, ST>(m, src, mom, x, y, z);
     }
 }
 
@@ -271,14 +285,13 @@ __global__ void __launch_bounds__(256)
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tiles[t];
         const Member m = members[tl.member];
-        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y;
-        if (x < m.nx && y < m.ny)
-            collide_mom_site<D, ORDER, ST, PSI>(m, dst, mom, x, y, tl.z0);
+        int x, y, z;
+        if (tile_site(m, tl, x, y, z)) collide_mom_site<D, ORDER, ST, PSI>(m, dst, mom, x, y, z);
     }
 }
 
-// ---- batched forms: a persistent grid walks a tile list; a tile is a
-// 64 x 4 x 1 block of sites of one member.
+// ---- batched forms: a persistent grid walks a tile list; a tile is a run of
+// 256 consecutive sites of one member (tile_site).
 template <int D, class ST>
 __global__ void __launch_bounds__(256)
     kb_density(const Member *__restrict__ members,
@@ -290,8 +303,8 @@ __global__ void __launch_bounds__(256)
         const Tile tl = tiles[t];
         const Member m = members[tl.member];
         advance_step_counter(m, t == 0);
-        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y, z = tl.z0;
-        if (x < m.nx && y < m.ny) {
+        int x, y, z;
+        if (tile_site(m, tl, x, y, z)) {
             R f[2][Lattice<D>::Q];
             pull_site<D, ST>(m, src, x, y, z, f);
             R nA, nB;
@@ -314,8 +327,8 @@ __global__ void __launch_bounds__(256)
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tiles[t];
         const Member m = members[tl.member];
-        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y, z = tl.z0;
-        if (x < m.nx && y < m.ny) {
+        int x, y, z;
+        if (tile_site(m, tl, x, y, z)) {
             R f[2][Lattice<D>::Q];
             pull_site<D, ST>(m, src, x, y, z, f);
             R nA, nB;
