@@ -120,7 +120,7 @@ template <int TX, int TY, int ORDER, class ST, int PSI>
 __device__ __forceinline__ void fused_collide_mom(
     const Member &m, const PopBuf<ST> &dst,
     float2 (*lds)[TY + 2 * FusedGeom<ORDER>::HR][TX + 2 * FusedGeom<ORDER>::HR],
-    const typename ST::R (&mom)[5], int k, int x0, int y0, int zc, int tx, int ty) {
+    const typename ST::R (&mom)[NMOM], int k, int x0, int y0, int zc, int tx, int ty) {
     using R = typename ST::R;
     using T = typename ST::T;
     R nA, nB, FA[3], FB[3];
@@ -131,6 +131,29 @@ __device__ __forceinline__ void fused_collide_mom(
     });
 }
 
+// Local position (lx, ly) of halo node h of a wx x wy tile with halo HR:
+// HR full rows above, then HR nodes left and right of every tile row, then
+// HR full rows below.
+template <int HR>
+__device__ __forceinline__ void halo_pos(int h, int wx, int wy, int &lx, int &ly) {
+    const int bw = wx + 2 * HR;
+    const int ntop = HR * bw, nmid = wy * 2 * HR;
+    if (h < ntop) {
+        ly = h / bw;
+        lx = h - ly * bw;
+    } else if (h < ntop + nmid) {
+        const int q = h - ntop;
+        ly = HR + q / (2 * HR);
+        const int c = q - (ly - HR) * 2 * HR;
+        lx = c < HR ? c : wx + c;
+    } else {
+        const int q = h - ntop - nmid;
+        const int r = q / bw;
+        ly = HR + wy + r;
+        lx = q - r * bw;
+    }
+}
+
 template <int TX, int TY, int ORDER, class ST, int PSI, int REPULL, int S>
 __device__ __forceinline__ void fused_plane(
     const Member &m, const PopBuf<ST> &src, const PopBuf<ST> &dst, float2 (*lds)[TY + 2 * FusedGeom<ORDER>::HR]
@@ -138,9 +161,8 @@ __device__ __forceinline__ void fused_plane(
     typename ST::R (&ring)[REPULL ? 1 : FusedGeom<ORDER>::NRING][2][19], int k, int x0,
     int y0, int z0, int wx, int wy, int tx, int ty, bool active) {
     using G = FusedGeom<ORDER>;
-    using L = Lattice<3>;
     using R = typename ST::R;
-    constexpr int HR = G::HR, ZR = G::ZR, BX = TX + 2 * HR;
+    constexpr int HR = G::HR, ZR = G::ZR;
     constexpr int NT = TX * TY;
     const int tid = ty * TX + tx;
     const int zl = wrap1(z0 - ZR + k, m.nz);
@@ -162,25 +184,10 @@ __device__ __forceinline__ void fused_plane(
         }
     }
     {
-        const int bw = wx + 2 * HR;
-        const int ntop = HR * bw, nmid = wy * 2 * HR;
-        const int nhalo = 2 * ntop + nmid;
+        const int nhalo = 2 * HR * (wx + 2 * HR) + wy * 2 * HR;
         for (int h = tid; h < nhalo; h += NT) {
             int lx, ly;
-            if (h < ntop) {
-                ly = h / bw;
-                lx = h - ly * bw;
-            } else if (h < ntop + nmid) {
-                const int q = h - ntop;
-                ly = HR + q / (2 * HR);
-                const int c = q - (ly - HR) * 2 * HR;
-                lx = c < HR ? c : wx + c;
-            } else {
-                const int q = h - ntop - nmid;
-                const int r = q / bw;
-                ly = HR + wy + r;
-                lx = q - r * bw;
-            }
+            halo_pos<HR>(h, wx, wy, lx, ly);
             const int gx = wrap1(x0 - HR + lx, m.nx);
             const int gy = wrap1(y0 - HR + ly, m.ny);
             R f[2][19];
@@ -216,28 +223,6 @@ __device__ __forceinline__ void static_for(F &&f) {
     }
 }
 
-// Local position (lx, ly) of halo node h of a wx x wy tile with halo HR:
-// HR full rows above, then HR nodes left and right of every tile row, then
-// HR full rows below.
-template <int HR>
-__device__ __forceinline__ void halo_pos(int h, int wx, int wy, int &lx, int &ly) {
-    const int bw = wx + 2 * HR;
-    const int ntop = HR * bw, nmid = wy * 2 * HR;
-    if (h < ntop) {
-        ly = h / bw;
-        lx = h - ly * bw;
-    } else if (h < ntop + nmid) {
-        const int q = h - ntop;
-        ly = HR + q / (2 * HR);
-        const int c = q - (ly - HR) * 2 * HR;
-        lx = c < HR ? c : wx + c;
-    } else {
-        const int q = h - ntop - nmid;
-        const int r = q / bw;
-        ly = HR + wy + r;
-        lx = q - r * bw;
-    }
-}
 
 // Tiles that span the whole x extent (wx == nx, one tile per row) take their
 // x halo from their own rows: the periodic images of the first and last HR
@@ -287,7 +272,6 @@ __device__ __forceinline__ void fused_tile_pipe(const Member &m,
     using G = FusedGeom<ORDER>;
     using R = typename ST::R;
     constexpr int HR = G::HR, ZR = G::ZR, NSLOT = G::NSLOT, NR = ZR + 2;
-    constexpr int NT = TX * TY;
     __shared__ float2 lds[NSLOT][TY + 2 * HR][TX + 2 * HR];
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int wx = min(TX, m.nx - x0), wy = min(TY, m.ny - y0);
@@ -403,10 +387,11 @@ __device__ __forceinline__ void fused_tile(const Member &m,
 
 // ---- omega = 1: moment ring
 // At tau = 1 the collision forgets the pre-collision populations except for
-// n_J and the total momentum j, so the march keeps those five moments per node
-// and plane instead of the 2Q populations.  The register ring shrinks from
-// (ZR + 1) x 2Q to (ZR + 1) x 5 values, which lets more waves share a SIMD
-// (and larger tiles fit), while the HBM traffic stays 2Q reads + 2Q writes.
+// n_J and the total momentum j, so the march keeps those moments per node and
+// plane (n_J as an exact value-plus-remainder pair, NMOM values) instead of
+// the 2Q populations.  The register ring shrinks from (ZR + 1) x 2Q to
+// (ZR + 1) x NMOM values, which lets more waves share a SIMD (and larger
+// tiles fit), while the HBM traffic stays 2Q reads + 2Q writes.
 template <int TX, int TY, int ORDER, class ST, int PSI>
 __device__ __forceinline__ void fused_tile_mom(const Member &m,
                                                const typename ST::T *__restrict__ src,
@@ -424,7 +409,7 @@ __device__ __forceinline__ void fused_tile_mom(const Member &m,
     const int nhalo = halo_count<HR>(wx, wy, full_row);
     const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
     const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
-    R mom[NR][5];
+    R mom[NR][NMOM];
     const int kend = len + 2 * ZR;
     for (int k0 = 0; k0 < kend; k0 += NR) {
         static_for<0, NR>([&](auto sc) {
@@ -485,7 +470,7 @@ __device__ __forceinline__ void fused_tile_mom_pipe(const Member &m,
     const int hgx = wrap1(x0 - HR + hlx, m.nx), hgy = wrap1(y0 - HR + hly, m.ny);
     const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
     const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
-    R mom[NR][5];  // plane z0 + p lives in mom[p % NR]
+    R mom[NR][NMOM];  // plane z0 + p lives in mom[p % NR]
     R fo[2][19], H[2][19];
 
     auto put_density = [&](float2(&plane)[TY + 2 * HR][TX + 2 * HR], int ly, int lx,
@@ -569,10 +554,11 @@ __device__ __forceinline__ void fused_tile_any(const Member &m,
 }
 
 // Waves per SIMD the compiler is asked to allow for: the population-ring
-// designs need most of the register file, the moment ring fits four waves,
-// its pipelined form (two planes of loads in flight) two.
+// designs need most of the register file, the moment ring fits three waves
+// (four for 1024-thread tiles, which the launch bound imposes), its
+// pipelined form (two planes of loads in flight) two.
 template <int VAR> constexpr int fused_waves() {
-    return VAR == 3 ? 4 : VAR == 4 ? 2 : 1;
+    return VAR == 3 ? 3 : VAR == 4 ? 2 : 1;
 }
 
 template <int TX, int TY, int ORDER, class ST, int PSI, int VAR>

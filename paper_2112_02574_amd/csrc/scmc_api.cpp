@@ -357,7 +357,7 @@ Plan plan_of(const std::vector<scmc_problem> &ps, int ntiles) {
         const size_t N = (size_t)p.nx * p.ny * p.nz;
         pop += align_up(2 * (size_t)lattice_q(p.lattice) * N *
                         storage_bytes(p.storage));
-        dens += align_up(5 * N * real_bytes(p.storage));
+        dens += align_up(7 * N * real_bytes(p.storage));
         nmax = std::max(nmax, N);
         nxmax = std::max(nxmax, (size_t)p.nx);
         nb = std::max(nb, stats_blocks(member_of(p)));
@@ -1153,7 +1153,7 @@ int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
         const size_t N = (size_t)L.m.N;
         pop_off += (long long)(align_up(2 * L.q * N * storage_bytes(v[i].storage)) /
                                storage_bytes(v[i].storage));
-        dens_off += (long long)(align_up(5 * N * real_bytes(v[i].storage)) /
+        dens_off += (long long)(align_up(7 * N * real_bytes(v[i].storage)) /
                                 real_bytes(v[i].storage));
         ms.push_back(L.m);
         b->lats.push_back(L);

@@ -11,7 +11,7 @@ namespace scmc {
 // pop + pop_off (element offset in the storage type) in both population
 // buffers, component-major: [J][i][z][y][x]; its density field lives at
 // dens + dens_off as [J][z][y][x] (the moment two-pass: (n_A, n_B) pairs
-// [z][y][x], then the momentum planes), with room for 5 fields.
+// [z][y][x], then the momentum planes and the remainders of n_J), with room for 7 fields.
 struct Member {
     int nx, ny, nz, N;
     long long pop_off;

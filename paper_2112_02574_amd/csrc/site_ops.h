@@ -180,7 +180,7 @@ __device__ __forceinline__ void site_collide(const Member &m,
         const R *F = J == 0 ? FA : FB;
         const R nJ = J == 0 ? nA : nB;
         const R uF = ux * F[0] + uy * F[1] + uz * F[2];
-        R moving = 0;
+        double moving = 0, nJx = (double)f[J][0];
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
             const R cx = (R)L::CX[i], cy = (R)L::CY[i], cz = (R)L::CZ[i];
@@ -192,36 +192,47 @@ __device__ __forceinline__ void site_collide(const Member &m,
             const R S = w * (R(3) * xF + R(9) * xu * xF - R(3) * uF);
             const R out = f[J][i] - omega * (f[J][i] - feq) + cf * S;
             sink(J, i, out, w * n0[J]);
-            moving += out;
+            moving += (double)out;
+            nJx += (double)f[J][i];
         }
-        // rest population from the mass balance sum_i f*_i = n_J (BGK and
-        // the Guo source conserve mass; rounded weights would not, by the
-        // same relative amount every step)
-        sink(J, 0, nJ - moving, (R)L::W[0] * n0[J]);
+        // rest population from the mass balance sum_i f*_i = sum_i f_i (BGK
+        // and the Guo source conserve mass), both sums exact in FP64: rounded
+        // weights and re-rounded sums would otherwise bias the mass by the
+        // same relative amount every step
+        sink(J, 0, (R)(nJx - moving), (R)L::W[0] * n0[J]);
     }
 }
 
 // Moments that the collision needs at omega = 1: n_J and the total momentum
-// j = sum_J sum_i f_i^J xi_i.
+// j = sum_J sum_i f_i^J xi_i.  n_J is summed in FP64 (exact for the 2Q
+// storage values) and kept as a pair: mom[J] = its nearest compute-precision
+// value, mom[5 + J] = the remainder.  The collision's rest population uses
+// the exact n_J to close the mass balance, so a steady site conserves mass
+// exactly instead of re-rounding the same sum the same way every step.
+constexpr int NMOM = 7;  // n_A, n_B, j_x, j_y, j_z, rem(n_A), rem(n_B)
+
 template <int D, class R>
 __device__ __forceinline__ void site_moments(const R (&f)[2][Lattice<D>::Q],
-                                             R (&mom)[5]) {
+                                             R (&mom)[NMOM]) {
     using L = Lattice<D>;
-    R nA = 0, nB = 0, jx = 0, jy = 0, jz = 0;
+    double nA = 0, nB = 0;
+    R jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        nA += f[0][i];
-        nB += f[1][i];
+        nA += (double)f[0][i];
+        nB += (double)f[1][i];
         const R t = f[0][i] + f[1][i];
         if (L::CX[i]) jx += (R)L::CX[i] * t;
         if (L::CY[i]) jy += (R)L::CY[i] * t;
         if (D == 3 && L::CZ[i]) jz += (R)L::CZ[i] * t;
     }
-    mom[0] = nA;
-    mom[1] = nB;
+    mom[0] = (R)nA;
+    mom[1] = (R)nB;
     mom[2] = jx;
     mom[3] = jy;
     mom[4] = jz;
+    mom[5] = (R)(nA - (double)mom[0]);
+    mom[6] = (R)(nB - (double)mom[1]);
 }
 
 // The collision at omega = 1 (tau = 1), where f* = f^eq(n_J, u) + S_i / 2
@@ -232,7 +243,7 @@ __device__ __forceinline__ void site_moments(const R (&f)[2][Lattice<D>::Q],
 //   O = w [3 n_J xi.u + 3/2 xi.F_J],   f*_xi = E + O, f*_-xi = E - O.
 // Every f*_i^J goes to sink(J, i, value, w_i n0_J).
 template <int D, class R, class Sink>
-__device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[5],
+__device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[NMOM],
                                              const R (&FA)[3], const R (&FB)[3],
                                              Sink &&sink) {
     using L = Lattice<D>;
@@ -250,7 +261,7 @@ __device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[5],
         const R nJ = J == 0 ? nA : nB;
         const R uF = ux * F[0] + uy * F[1] + uz * F[2];
         const R a = nJ * (R(1) - R(1.5) * uu) - R(1.5) * uF;
-        R moving = 0;
+        double moving = 0;
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
             const int ib = OP.opp[i];
@@ -263,14 +274,17 @@ __device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[5],
             const R t = nJ * xu;
             const R E = w * (a + R(4.5) * xu * (t + xF));
             const R O = w * (R(3) * t + R(1.5) * xF);
-            sink(J, i, E + O, w * n0[J]);
-            sink(J, ib, E - O, w * n0[J]);
-            moving += (E + O) + (E - O);
+            const R fp = E + O, fm = E - O;
+            sink(J, i, fp, w * n0[J]);
+            sink(J, ib, fm, w * n0[J]);
+            moving += (double)fp + (double)fm;
         }
-        // the rest population closes the mass balance sum_i f*_i = n_J, which
-        // the rounded weights (their binary sum is not exactly 1) would bias
-        // by the same relative amount every step
-        sink(J, 0, nJ - moving, (R)L::W[0] * n0[J]);
+        // the rest population closes the mass balance sum_i f*_i = n_J with
+        // the exact n_J: rounded weights (their binary sum is not exactly 1)
+        // and re-rounded sums would otherwise bias the mass by the same
+        // relative amount every step
+        const double nJx = (double)nJ + (double)mom[5 + J];
+        sink(J, 0, (R)(nJx - moving), (R)L::W[0] * n0[J]);
     }
 }
 

@@ -12,10 +12,11 @@
 //
 // At tau = 1 the second pass need not pull again: the collision then depends
 // on the populations only through n_J and the total momentum j.  Pass 1
-// (k_moments) stores (n_A, n_B) pairs followed by the j planes; pass 2
-// (k_collide_mom) reads the node's moments and the stencil's concentration
-// pairs and stores f*.  Per site it moves 2Q reads + 2Q writes of populations
-// plus (2 + d) moment writes and reads, instead of 4Q reads + 2Q writes.
+// (k_moments) stores (n_A, n_B) pairs, the j planes and the FP64 remainders
+// of n_A, n_B; pass 2 (k_collide_mom) reads the node's moments and the
+// stencil's concentration pairs and stores f*.  Per site it moves 2Q reads +
+// 2Q writes of populations plus 7 moment writes and reads (28 B each way in
+// FP32), instead of 4Q reads + 2Q writes.
 #include <type_traits>
 
 #include "site_ops.h"
@@ -83,14 +84,15 @@ __global__ void __launch_bounds__(256)
 template <class R> using Pair = typename std::conditional<std::is_same<R, float>::value,
                                                           float2, double2>::type;
 
-// moment field of a member: (n_A, n_B) pairs [z][y][x], then j_x, j_y (, j_z)
+// moment field of a member: (n_A, n_B) pairs [z][y][x], then the planes j_x,
+// j_y (, j_z), then the remainders of n_A and n_B (planes 5 and 6)
 template <int D, class ST>
 __device__ __forceinline__ void moments_site(const Member &m,
                                              const typename ST::T *__restrict__ src,
                                              typename ST::R *__restrict__ mom, int x,
                                              int y, int z) {
     using R = typename ST::R;
-    R f[2][Lattice<D>::Q], mm[5];
+    R f[2][Lattice<D>::Q], mm[NMOM];
     pull_site<D, ST>(m, src, x, y, z, f);
     site_moments<D, R>(f, mm);
     const long s = ((long)z * m.ny + y) * m.nx + x;
@@ -101,6 +103,8 @@ __device__ __forceinline__ void moments_site(const Member &m,
     reinterpret_cast<Pair<R> *>(base)[s] = pr;
 #pragma unroll
     for (int c = 0; c < D; ++c) base[(2 + c) * (long)m.N + s] = mm[2 + c];
+    base[5 * (long)m.N + s] = mm[5];
+    base[6 * (long)m.N + s] = mm[6];
 }
 
 template <int D, int ORDER, class ST, int PSI>
@@ -113,7 +117,7 @@ __device__ __forceinline__ void collide_mom_site(const Member &m,
     const Pair<R> *pairs = reinterpret_cast<const Pair<R> *>(base);
     const long s = ((long)z * m.ny + y) * m.nx + x;
     const Pair<R> own = pairs[s];
-    R mm[5] = {own.x, own.y, 0, 0, 0};
+    R mm[NMOM] = {own.x, own.y, 0, 0, 0, base[5 * (long)m.N + s], base[6 * (long)m.N + s]};
 #pragma unroll
     for (int c = 0; c < D; ++c) mm[2 + c] = base[(2 + c) * (long)m.N + s];
     R FA[3], FB[3];
@@ -144,7 +148,7 @@ __device__ __forceinline__ void moments_site_buf(const Member &m, const PopBuf<S
                                                  typename ST::R *__restrict__ mom, int x,
                                                  int y, int z) {
     using R = typename ST::R;
-    R f[2][19], mm[5];
+    R f[2][19], mm[NMOM];
     pull_site_buf<ST>(m, sb, x, y, z, f);
     site_moments<3, R>(f, mm);
     const int s = (z * m.ny + y) * m.nx + x;
@@ -152,6 +156,8 @@ __device__ __forceinline__ void moments_site_buf(const Member &m, const PopBuf<S
     reinterpret_cast<Pair<R> *>(base)[s] = Pair<R>{mm[0], mm[1]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) base[(2 + c) * (long)m.N + s] = mm[2 + c];
+    base[5 * (long)m.N + s] = mm[5];
+    base[6 * (long)m.N + s] = mm[6];
 }
 
 template <int ORDER, class ST, int PSI>
@@ -164,7 +170,7 @@ __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopB
     const Pair<R> *pairs = reinterpret_cast<const Pair<R> *>(base);
     const int s = (z * m.ny + y) * m.nx + x;
     const Pair<R> own = pairs[s];
-    R mm[5] = {own.x, own.y, 0, 0, 0};
+    R mm[NMOM] = {own.x, own.y, 0, 0, 0, base[5 * (long)m.N + s], base[6 * (long)m.N + s]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) mm[2 + c] = base[(2 + c) * (long)m.N + s];
     R FA[3], FB[3];
