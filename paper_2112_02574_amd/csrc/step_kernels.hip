@@ -12,11 +12,11 @@
 //
 // At tau = 1 the second pass need not pull again: the collision then depends
 // on the populations only through n_J and the total momentum j.  Pass 1
-// (k_moments) stores (n_A, n_B) pairs, the j planes and the FP64 remainders
-// of n_A, n_B; pass 2 (k_collide_mom) reads the node's moments and the
-// stencil's concentration pairs and stores f*.  Per site it moves 2Q reads +
-// 2Q writes of populations plus 7 moment writes and reads (28 B each way in
-// FP32), instead of 4Q reads + 2Q writes.
+// (k_moments) stores (n_A, n_B) pairs, the j planes and the packed FP64
+// remainders of n_A, n_B; pass 2 (k_collide_mom) reads the node's moments and
+// the stencil's concentration pairs and stores f*.  Per site it moves 2Q reads
+// + 2Q writes of populations plus 24 B of moments each way (FP32), instead of
+// 4Q reads + 2Q writes.
 #include <type_traits>
 
 #include "site_ops.h"
@@ -84,8 +84,44 @@ __global__ void __launch_bounds__(256)
 template <class R> using Pair = typename std::conditional<std::is_same<R, float>::value,
                                                           float2, double2>::type;
 
+// The FP64 remainders of n_A, n_B (at most half an ulp of the stored value)
+// travel as two halves of one 32-bit word, in units of that ulp: 11 bits of
+// the remainder keep the rest population's mass closure exact to 2^-12 ulp,
+// far inside its own rounding.  FP64 compute has no remainder.
+template <class R>
+__device__ __forceinline__ unsigned pack_rem(const R (&mm)[NMOM]) {
+    if constexpr (std::is_same<R, double>::value) {
+        return 0u;
+    } else {
+        unsigned out = 0;
+#pragma unroll
+        for (int J = 0; J < 2; ++J) {
+            int e;
+            frexpf(mm[J], &e);
+            const float q = ldexpf(mm[5 + J], 24 - e);  // remainder / ulp(n_J)
+            out |= (unsigned)__half_as_ushort(__float2half_rn(q)) << (16 * J);
+        }
+        return out;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void unpack_rem(unsigned w, R (&mm)[NMOM]) {
+    if constexpr (std::is_same<R, double>::value) {
+        mm[5] = mm[6] = 0;
+    } else {
+#pragma unroll
+        for (int J = 0; J < 2; ++J) {
+            int e;
+            frexpf(mm[J], &e);
+            const float q = __half2float(__ushort_as_half((unsigned short)(w >> (16 * J))));
+            mm[5 + J] = ldexpf(q, e - 24);
+        }
+    }
+}
+
 // moment field of a member: (n_A, n_B) pairs [z][y][x], then the planes j_x,
-// j_y (, j_z), then the remainders of n_A and n_B (planes 5 and 6)
+// j_y (, j_z), then the packed remainders of n_A and n_B (plane 5)
 template <int D, class ST>
 __device__ __forceinline__ void moments_site(const Member &m,
                                              const typename ST::T *__restrict__ src,
@@ -103,8 +139,7 @@ __device__ __forceinline__ void moments_site(const Member &m,
     reinterpret_cast<Pair<R> *>(base)[s] = pr;
 #pragma unroll
     for (int c = 0; c < D; ++c) base[(2 + c) * (long)m.N + s] = mm[2 + c];
-    base[5 * (long)m.N + s] = mm[5];
-    base[6 * (long)m.N + s] = mm[6];
+    reinterpret_cast<unsigned *>(base + 5 * (long)m.N)[s] = pack_rem<R>(mm);
 }
 
 template <int D, int ORDER, class ST, int PSI>
@@ -117,9 +152,10 @@ __device__ __forceinline__ void collide_mom_site(const Member &m,
     const Pair<R> *pairs = reinterpret_cast<const Pair<R> *>(base);
     const long s = ((long)z * m.ny + y) * m.nx + x;
     const Pair<R> own = pairs[s];
-    R mm[NMOM] = {own.x, own.y, 0, 0, 0, base[5 * (long)m.N + s], base[6 * (long)m.N + s]};
+    R mm[NMOM] = {own.x, own.y, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int c = 0; c < D; ++c) mm[2 + c] = base[(2 + c) * (long)m.N + s];
+    unpack_rem<R>(reinterpret_cast<const unsigned *>(base + 5 * (long)m.N)[s], mm);
     R FA[3], FB[3];
     site_force_fn<D, ORDER, PSI, R>(m, x, y, z, own.x, own.y, FA, FB,
                                     [&](int t, R &a, R &b) {
@@ -156,8 +192,7 @@ __device__ __forceinline__ void moments_site_buf(const Member &m, const PopBuf<S
     reinterpret_cast<Pair<R> *>(base)[s] = Pair<R>{mm[0], mm[1]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) base[(2 + c) * (long)m.N + s] = mm[2 + c];
-    base[5 * (long)m.N + s] = mm[5];
-    base[6 * (long)m.N + s] = mm[6];
+    reinterpret_cast<unsigned *>(base + 5 * (long)m.N)[s] = pack_rem<R>(mm);
 }
 
 template <int ORDER, class ST, int PSI>
@@ -170,9 +205,10 @@ __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopB
     const Pair<R> *pairs = reinterpret_cast<const Pair<R> *>(base);
     const int s = (z * m.ny + y) * m.nx + x;
     const Pair<R> own = pairs[s];
-    R mm[NMOM] = {own.x, own.y, 0, 0, 0, base[5 * (long)m.N + s], base[6 * (long)m.N + s]};
+    R mm[NMOM] = {own.x, own.y, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int c = 0; c < 3; ++c) mm[2 + c] = base[(2 + c) * (long)m.N + s];
+    unpack_rem<R>(reinterpret_cast<const unsigned *>(base + 5 * (long)m.N)[s], mm);
     R FA[3], FB[3];
     site_force_fn<3, ORDER, PSI, R>(m, x, y, z, own.x, own.y, FA, FB,
                                     [&](int t, R &a, R &b) {
