@@ -7,9 +7,10 @@ profile of Sec. 4 between the bulk concentrations of a converged flat
 interface (the paper's two-stage initialisation, first stage run on the GPU
 before timing).  A timed step is one lattice update of both components
 (stream + concentrations + Shan-Chen force + common velocity + BGK/Guo
-collide); the FP64 statistics and the pressure-tensor / sigma[R] / R_s
-reductions run at the paper's monitoring cadence (every 2^11 steps, Sec. 4)
-and at least once inside the timed region.
+collide); the FP64 statistics, the pressure-tensor / sigma[R] / R_s
+reductions and the convergence criteria (Delta P change, du, droplet centre)
+run at the paper's monitoring cadence (every 2^11 steps, Sec. 4) and at least
+once inside the timed region.
 
 Prints one JSON line: MLUPS (million lattice-site updates per second, both
 components), the roofline of the step kernel (algorithmic bytes 4 Q s per
@@ -288,8 +289,10 @@ def run(args):
         step_ms += ev0.elapsed_time(ev1)
         done += chunk
         # monitoring reductions (FP64): statistics, pressure tensor, sigma[R], R_s
+        # and the convergence criteria of Sec. 4 (Delta P change, du, centre)
         stats = sim.scmc_stats_get()
         obs = sim.scmc_observables(scmc.OBS_DROPLET, R0)
+        conv = sim.scmc_convergence_check(R0)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
@@ -323,7 +326,10 @@ def run(args):
         "observables": {"dP": _finite(obs["dP"]), "R_s": _finite(obs["R_s"]),
                         "sigma_s": _finite(obs["sigma_s"]), "step": obs["step"],
                         "mass": stats["mass"].tolist(), "max_u": _finite(stats["max_u"]),
-                        "init_bulk": [round(v, 12) for v in bulk], "flat_steps": flat_steps},
+                        "init_bulk": [round(v, 12) for v in bulk], "flat_steps": flat_steps,
+                        "dP_change": _finite(conv["dP_change"]), "du": _finite(conv["du"]),
+                        "com_offset": _finite(conv["com_offset"]),
+                        "converged": conv["converged"]},
     }
     sim.close()
     if args.variant_steps > 0:

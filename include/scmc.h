@@ -194,6 +194,35 @@ int scmc_stats_get(scmc_sim *s, scmc_stats *out);
 int scmc_observables(scmc_sim *s, int kind, double R0, scmc_obs *out,
                      double *PN, double *PT);
 
+/* Convergence monitor of a droplet run (Sec. 4), meant to be called every
+ * dt steps (the paper: dt = 2^11).  Each call evaluates the droplet
+ * observables at R0 (as scmc_observables), the FP64 velocity field and the
+ * centre of the rich component's excess concentration, and compares with the
+ * previous call on this handle (the previous velocity field is kept in the
+ * workspace; setting a new state forgets it):
+ *   dP_change = |dP(t) - dP(t_prev)| / |dP(t_prev)|            (criterion i)
+ *   du = (1/N) sum_x sum_a |u_a(x, t) - u_a(x, t_prev)|       (criterion ii)
+ * converged = dP_change < tol_dP or du < tol_du (the paper: 1e-5, 1e-12); on
+ * the first call there is no comparison (NaN, not converged).  The rich
+ * component is the one with the larger concentration at the centre node; its
+ * excess is n_rich(x) - n_rich at the far node, and com[a] = c_a +
+ * sum ex (x_a - c_a) / sum ex with c_a = floor(L_a / 2) (the paper analyses
+ * a run only if every |com_a - c_a| < 1e-3). */
+typedef struct {
+    double dP, dP_change, du;
+    double com[3];
+    double com_offset;   /* max_a |com_a - c_a| */
+    int rich;            /* 0: A-rich droplet, 1: B-rich */
+    int converged;
+    int64_t step, prev_step;
+} scmc_convergence;
+int scmc_convergence_check(scmc_sim *s, double R0, double tol_dP, double tol_du,
+                           scmc_convergence *out);
+/* Steps in chunks of dt with a check after each (and one before the first),
+ * until converged or max_steps have run; *out holds the last check. */
+int scmc_run_to_convergence(scmc_sim *s, double R0, int64_t dt, int64_t max_steps,
+                            double tol_dP, double tol_du, scmc_convergence *out);
+
 /* Flat-interface steady state (Sec. 4: the droplet runs start from the bulk
  * concentrations of a converged flat interface).  Runs the problem's lattice,
  * stencil, couplings, tau, psi and storage on a transverse-thin periodic box

@@ -265,3 +265,31 @@ def flat_equilibrium(dim, stencil, g, psi_self=PSI_N, tau=1.0, lx=128,
         if done > k and change <= tol:
             break
     return prev.tolist(), done
+
+
+def delta_u(u1, u0):
+    """Convergence criterion (ii) of Sec. 4: the mean over sites of
+    sum_a |u_a(x, t + dt) - u_a(x, t)|; u arrays shaped (3, *box)."""
+    u1 = np.asarray(u1, dtype=np.float64)
+    u0 = np.asarray(u0, dtype=np.float64)
+    n_sites = u1[0].size
+    return float(np.abs(u1 - u0).sum() / n_sites)
+
+
+def excess_com(n, shape):
+    """Centre of a droplet (Sec. 4 requires it within 1e-3 of the box centre):
+    the component richer at the centre node c = floor(L/2) per axis, its
+    excess concentration over the value at the far node (c + floor(L/2)) mod L,
+    and the excess-weighted mean of x - c per axis, plus c.  n has shape
+    (2, nz, ny, nx); returns (com[3] as x, y, z; rich component)."""
+    nz, ny, nx = shape
+    c = (nz // 2, ny // 2, nx // 2)
+    far = ((c[0] + nz // 2) % nz, (c[1] + ny // 2) % ny, (c[2] + nx // 2) % nx)
+    rich = 1 if n[1][c] > n[0][c] else 0
+    ex = n[rich] - n[rich][far]
+    total = ex.sum()
+    z, y, x = np.meshgrid(np.arange(nz) - c[0], np.arange(ny) - c[1], np.arange(nx) - c[2],
+                          indexing="ij")
+    com = [c[2] + (ex * x).sum() / total, c[1] + (ex * y).sum() / total,
+           c[0] + (ex * z).sum() / total if nz > 1 else 0.0]
+    return np.array(com), rich

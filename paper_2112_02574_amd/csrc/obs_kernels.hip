@@ -357,6 +357,75 @@ static dim3 ob_grid(const Member &m) {
     return dim3((m.nx + OB_BX - 1) / OB_BX, (m.ny + OB_BY - 1) / OB_BY, m.nz);
 }
 
+// ---- convergence monitor (Sec. 4): delta u between two velocity fields
+// and the centre of the rich component's excess concentration.
+// slots: 0 sum_x sum_a |u_a - u0_a|, 1 sum_x ex, 2..4 sum_x ex (x_a - c_a),
+// with ex = n_rich(x) - n_rich_out and c_a = floor(L_a / 2).
+constexpr int NMON = 5;
+
+__global__ void __launch_bounds__(OB_THREADS)
+    k_monitor(Member m, int dim, const double *__restrict__ dens,
+              const double *__restrict__ u, const double *__restrict__ u0, int rich,
+              double n_out, double *__restrict__ partials) {
+    __shared__ double red[NMON][OB_THREADS];
+    const int tid = threadIdx.y * OB_BX + threadIdx.x;
+    const int x = blockIdx.x * OB_BX + threadIdx.x;
+    const int y = blockIdx.y * OB_BY + threadIdx.y;
+    const int z = blockIdx.z;
+    double v[NMON] = {0, 0, 0, 0, 0};
+    if (x < m.nx && y < m.ny) {
+        const long s = ((long)z * m.ny + y) * m.nx + x;
+        if (u0)
+            for (int a = 0; a < dim; ++a) v[0] += fabs(u[a * (long)m.N + s] - u0[a * (long)m.N + s]);
+        const double ex = dens[rich * (long)m.N + s] - n_out;
+        v[1] = ex;
+        v[2] = ex * (x - m.nx / 2);
+        v[3] = ex * (y - m.ny / 2);
+        v[4] = dim == 3 ? ex * (z - m.nz / 2) : 0.0;
+    }
+    for (int k = 0; k < NMON; ++k) red[k][tid] = v[k];
+    __syncthreads();
+    for (int h = OB_THREADS / 2; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int k = 0; k < NMON; ++k) red[k][tid] += red[k][tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const long b = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        for (int k = 0; k < NMON; ++k) partials[b * NMON + k] = red[k][0];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+    k_monitor_final(const double *__restrict__ partials, int nblocks,
+                    double *__restrict__ out) {
+    __shared__ double red[NMON][256];
+    const int tid = threadIdx.x;
+    double v[NMON] = {0, 0, 0, 0, 0};
+    for (int b = tid; b < nblocks; b += 256)
+        for (int k = 0; k < NMON; ++k) v[k] += partials[(long)b * NMON + k];
+    for (int k = 0; k < NMON; ++k) red[k][tid] = v[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int k = 0; k < NMON; ++k) red[k][tid] += red[k][tid + h];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int k = 0; k < NMON; ++k) out[k] = red[k][0];
+}
+
+hipError_t launch_monitor(const Member &m, int dim, const double *dens64, const double *u,
+                          const double *u0, int rich, double n_out, double *partials,
+                          double *out, hipStream_t st) {
+    const dim3 g((m.nx + OB_BX - 1) / OB_BX, (m.ny + OB_BY - 1) / OB_BY, m.nz);
+    hipLaunchKernelGGL(k_monitor, g, dim3(OB_BX, OB_BY), 0, st, m, dim, dens64, u, u0,
+                       rich, n_out, partials);
+    const int nb = (int)(g.x * g.y * g.z);
+    hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(256), 0, st, partials, nb, out);
+    return hipGetLastError();
+}
+
 int stats_blocks(const Member &m) {
     const dim3 g = ob_grid(m);
     return (int)(g.x * g.y * g.z);

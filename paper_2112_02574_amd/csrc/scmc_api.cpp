@@ -156,6 +156,7 @@ struct Common {
     void *dens = nullptr;
     double *dens64 = nullptr;
     double *vel64 = nullptr;
+    double *velprev = nullptr;  // velocity field of the previous convergence check
     double *partials = nullptr;
     double *small = nullptr;  // stats / line / flat outputs
     unsigned *ctr = nullptr;  // step counter of the stochastic rounding
@@ -172,6 +173,9 @@ struct Common {
 struct scmc_sim {
     Common c;
     Lat lat;
+    bool have_prev = false;  // convergence monitor: a previous check exists
+    double prev_dP = 0;
+    int64_t prev_step = 0;
 };
 
 struct scmc_batch {
@@ -346,7 +350,7 @@ int public_kernel(int kernel, int variant, int mom) {
 }
 
 struct Plan {
-    size_t pop, dens, dens64, vel64, partials, small, ctr, members, tiles, total;
+    size_t pop, dens, dens64, vel64, velprev, partials, small, ctr, members, tiles, total;
 };
 
 Plan plan_of(const std::vector<scmc_problem> &ps, int ntiles) {
@@ -366,12 +370,13 @@ Plan plan_of(const std::vector<scmc_problem> &ps, int ntiles) {
     pl.dens = dens;
     pl.dens64 = align_up(2 * nmax * 8);
     pl.vel64 = align_up(3 * nmax * 8);
+    pl.velprev = ps.size() == 1 ? align_up(3 * nmax * 8) : 0;
     pl.partials = align_up((size_t)nb * 9 * 8);
     pl.small = align_up((3 * (nxmax / 2 + 1) + 3 + 2 * nxmax + 1 + 16) * 8);
     pl.ctr = align_up(sizeof(unsigned));
     pl.members = ps.size() > 1 ? align_up(ps.size() * sizeof(Member)) : 0;
     pl.tiles = ntiles > 0 ? align_up((size_t)ntiles * sizeof(Tile)) : 0;
-    pl.total = 2 * pl.pop + pl.dens + pl.dens64 + pl.vel64 + pl.partials +
+    pl.total = 2 * pl.pop + pl.dens + pl.dens64 + pl.vel64 + pl.velprev + pl.partials +
                pl.small + pl.ctr + pl.members + pl.tiles;
     return pl;
 }
@@ -388,6 +393,8 @@ void bind(Common &c, const Plan &pl, char *ws, int nblocks) {
     p += pl.dens64;
     c.vel64 = (double *)p;
     p += pl.vel64;
+    c.velprev = pl.velprev ? (double *)p : nullptr;
+    p += pl.velprev;
     c.partials = (double *)p;
     p += pl.partials;
     c.small = (double *)p;
@@ -864,6 +871,7 @@ int scmc_set_density(scmc_sim *s, const double *nA, const double *nB) {
     int rc = set_density_impl(s->c, s->lat, nA, nB, s->c.pop[0]);
     if (!rc) rc = set_step_counter(s->c, 0);
     if (rc) return rc;
+    s->have_prev = false;
     s->c.cur = 0;
     s->c.step = 0;
     s->c.initialized = true;
@@ -879,6 +887,7 @@ int scmc_set_populations(scmc_sim *s, const double *f, int64_t step) {
     int rc = upload_state(s->c, s->lat, f, s->c.pop[0]);
     if (!rc) rc = set_step_counter(s->c, step);
     if (rc) return rc;
+    s->have_prev = false;
     s->c.cur = 0;
     s->c.step = step;
     s->c.initialized = true;
@@ -941,6 +950,71 @@ int scmc_observables(scmc_sim *s, int kind, double R0, scmc_obs *out,
     if (!s->c.initialized) return fail(s->c, SCMC_ESTATE, "state not set");
     return obs_impl(s->c, s->lat, s->c.pop[s->c.cur], kind, R0, out, PN, PT,
                     s->c.step);
+}
+
+int scmc_convergence_check(scmc_sim *s, double R0, double tol_dP, double tol_du,
+                           scmc_convergence *out) {
+    if (!s || !out) return SCMC_EINVAL;
+    Common &c = s->c;
+    if (!c.initialized) return fail(c, SCMC_ESTATE, "state not set");
+    const Lat &L = s->lat;
+    const Member m = obs_member(L);
+    const void *pop = c.pop[c.cur];
+    scmc_obs o;
+    int rc = obs_impl(c, L, pop, SCMC_OBS_DROPLET, R0, &o, nullptr, nullptr, c.step);
+    if (rc) return rc;  // obs_impl leaves the FP64 densities in dens64
+    const long N = m.N;
+    const long centre = ((long)(m.nz / 2) * m.ny + m.ny / 2) * m.nx + m.nx / 2;
+    const long far = ((long)((m.nz / 2 + m.nz / 2) % m.nz) * m.ny + (m.ny / 2 + m.ny / 2) % m.ny) *
+                         m.nx + (m.nx / 2 + m.nx / 2) % m.nx;
+    double h[4];
+    HIPCHK(c, hipMemcpyAsync(&h[0], c.dens64 + centre, 8, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipMemcpyAsync(&h[1], c.dens64 + N + centre, 8, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipMemcpyAsync(&h[2], c.dens64 + far, 8, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipMemcpyAsync(&h[3], c.dens64 + N + far, 8, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    const int rich = h[1] > h[0] ? 1 : 0;
+    HIPCHK(c, launch_velocity64(c.key, m, pop, c.dens64, c.vel64, c.stream));
+    HIPCHK(c, launch_monitor(m, L.dim, c.dens64, c.vel64, s->have_prev ? c.velprev : nullptr,
+                             rich, h[2 + rich], c.partials, c.small, c.stream));
+    double r[5];
+    HIPCHK(c, hipMemcpyAsync(r, c.small, sizeof r, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipMemcpyAsync(c.velprev, c.vel64, 3 * N * 8, hipMemcpyDeviceToDevice, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+    const double nan = std::nan("");
+    std::memset(out, 0, sizeof *out);
+    out->dP = o.dP;
+    out->dP_change = s->have_prev ? std::fabs(o.dP - s->prev_dP) / std::fabs(s->prev_dP) : nan;
+    out->du = s->have_prev ? r[0] / (double)N : nan;
+    const int ext[3] = {m.nx, m.ny, m.nz};
+    out->com_offset = 0;
+    for (int a = 0; a < 3; ++a) {
+        const double off = a < L.dim ? r[2 + a] / r[1] : 0.0;
+        out->com[a] = ext[a] / 2 + off;
+        out->com_offset = std::max(out->com_offset, std::fabs(off));
+    }
+    out->rich = rich;
+    out->step = c.step;
+    out->prev_step = s->have_prev ? s->prev_step : -1;
+    out->converged = s->have_prev && (out->dP_change < tol_dP || out->du < tol_du);
+    s->have_prev = true;
+    s->prev_dP = o.dP;
+    s->prev_step = c.step;
+    return SCMC_OK;
+}
+
+int scmc_run_to_convergence(scmc_sim *s, double R0, int64_t dt, int64_t max_steps,
+                            double tol_dP, double tol_du, scmc_convergence *out) {
+    if (!s || !out || dt < 1 || max_steps < 0) return SCMC_EINVAL;
+    int rc = scmc_convergence_check(s, R0, tol_dP, tol_du, out);
+    int64_t done = 0;
+    while (!rc && !out->converged && done < max_steps) {
+        const int64_t k = std::min(dt, max_steps - done);
+        rc = scmc_step(s, k);
+        done += k;
+        if (!rc) rc = scmc_convergence_check(s, R0, tol_dP, tol_du, out);
+    }
+    return rc;
 }
 
 int scmc_config(scmc_sim *s, int *kernel, int *tile) {

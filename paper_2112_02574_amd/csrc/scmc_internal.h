@@ -96,6 +96,12 @@ hipError_t launch_velocity64(const StepKey &k, const Member &m, const void *pop,
 // centre; out[3*(rmax+1)] = P_in, [+1] = P_out, [+2] = C_d
 hipError_t launch_line(const StepKey &k, const Member &m, const double *dens64,
                        double *out, hipStream_t st);
+// convergence monitor: out[0] = sum |u - u0| (u0 nullable), out[1] = sum of
+// the rich component's excess concentration, out[2..4] = its first moments
+// about the centre node; partials as for the stats
+hipError_t launch_monitor(const Member &m, int dim, const double *dens64, const double *u,
+                          const double *u0, int rich, double n_out, double *partials,
+                          double *out, hipStream_t st);
 // flat: out[0..nx) = <P^xx>_yz, out[nx..2nx) = <P^yy>_yz, out[2nx] = sigma0
 hipError_t launch_flat(const StepKey &k, const Member &m, const double *dens64,
                        double *out, hipStream_t st);

@@ -69,6 +69,20 @@ class Obs(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Convergence(ctypes.Structure):
+    _fields_ = [("dP", ctypes.c_double), ("dP_change", ctypes.c_double),
+                ("du", ctypes.c_double), ("com", ctypes.c_double * 3),
+                ("com_offset", ctypes.c_double), ("rich", ctypes.c_int),
+                ("converged", ctypes.c_int), ("step", ctypes.c_int64),
+                ("prev_step", ctypes.c_int64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["com"] = np.array(self.com[:])
+        d["converged"] = bool(self.converged)
+        return d
+
+
 _lib = None
 _SYMBOLS = {
     "scmc_problem_init": ([ctypes.POINTER(Problem)], ctypes.c_int),
@@ -104,6 +118,11 @@ _SYMBOLS = {
     "scmc_autotune": ([ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "scmc_batch_autotune": ([ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "scmc_config": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "scmc_convergence_check": ([ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.POINTER(Convergence)], ctypes.c_int),
+    "scmc_run_to_convergence": ([ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_double, ctypes.c_double, ctypes.POINTER(Convergence)],
+                                ctypes.c_int),
     "scmc_flat_workspace_bytes": ([ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
                                   ctypes.c_int),
     "scmc_flat_equilibrium": ([ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
@@ -303,6 +322,19 @@ class Sim:
         d = o.as_dict()
         d["PN"], d["PT"] = PN, PT
         return d
+
+    def scmc_convergence_check(self, R0, tol_dP=1e-5, tol_du=1e-12):
+        o = Convergence()
+        self._check(lib().scmc_convergence_check(self.h, float(R0), float(tol_dP), float(tol_du),
+                                                  ctypes.byref(o)), "scmc_convergence_check")
+        return o.as_dict()
+
+    def scmc_run_to_convergence(self, R0, dt=2048, max_steps=200000, tol_dP=1e-5, tol_du=1e-12):
+        o = Convergence()
+        self._check(lib().scmc_run_to_convergence(self.h, float(R0), int(dt), int(max_steps),
+                                                   float(tol_dP), float(tol_du), ctypes.byref(o)),
+                    "scmc_run_to_convergence")
+        return o.as_dict()
 
     def scmc_config(self):
         k = ctypes.c_int()

@@ -47,8 +47,11 @@ def _bytes(p):
 def test_workspace_planner():
     p = scmc.problem(scmc.D3Q19, scmc.E6, (128, 128, 128), storage=scmc.F32)
     n = _bytes(p)
-    pops = 2 * 2 * 19 * 128 ** 3 * 4
-    assert pops < n < pops * 1.3
+    N = 128 ** 3
+    pops = 2 * 2 * 19 * N * 4
+    # two population buffers, the 7-field moment field (FP32), FP64 densities,
+    # FP64 velocity and the monitor's previous velocity, plus small buffers
+    assert pops < n < pops + (7 * 4 + 2 * 8 + 2 * 3 * 8) * N + (1 << 20)
     p16 = scmc.problem(scmc.D3Q19, scmc.E6, (128, 128, 128), storage=scmc.F16_OFF)
     assert _bytes(p16) < n
     p64 = scmc.problem(scmc.D3Q19, scmc.E6, (128, 128, 128), storage=scmc.F64)

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_2112_02574_amd import inputs
 from tests.naive_lbm import Naive
 
 STENCILS = [(2, 4), (2, 6), (2, 8), (3, 4), (3, 6)]
@@ -146,3 +147,42 @@ def test_conservation_over_run(dim, order):
     assert np.abs(s1["momentum"]).max() < 1e-11 * s0["mass"].sum()
     assert s1["n_nonfinite"] == 0
     assert s1["max_u"] > 1e-5
+
+
+def test_delta_u_of_a_decaying_shear_wave():
+    """Criterion (ii) of Sec. 4 on u_x(y) = U sin(k y) exp(-nu k^2 t): the mean
+    of |u(t + dt) - u(t)| is (2/pi) U exp(-nu k^2 t) (1 - exp(-nu k^2 dt))
+    (mean of |sin| over a period is 2/pi), and a state at rest gives 0."""
+    L, tau = 64, 0.8
+    o = O.Oracle(2, 4, (L, 4), tau=tau, g=((0.0, 0.0), (0.0, 0.0)))
+    k, U = 2 * np.pi / L, 1e-4
+    f = np.zeros((2, 9, 1, L, 4))
+    for J, nJ in enumerate((0.6, 0.4)):
+        for iy in range(L):
+            f[J, :, 0, iy, :] = O.equilibrium(2, nJ, np.array([U * np.sin(k * iy), 0.0, 0.0]))[:, None]
+    o.set_populations(f)
+    o.run(200)
+    u0 = o.velocity()
+    o.run(400)
+    u1 = o.velocity()
+    nu = (tau - 0.5) / 3.0
+    want = 2 / np.pi * U * np.exp(-nu * k * k * 200) * (1 - np.exp(-nu * k * k * 400))
+    assert abs(O.delta_u(u1, u0) / want - 1) < 5e-3
+    assert O.delta_u(u1, u1) == 0.0
+
+
+def test_excess_com_locates_the_droplet():
+    """A droplet centred on c = floor(L/2) has its centre there; the same
+    droplet rolled by (2, -1, 1) nodes moves it by exactly that.  (With even
+    L the cell [c - L/2, c + L/2) is one node short of symmetric; the tanh
+    tails there, ~exp(-2 (L/2 - R - shift)), offset the centre slightly.)"""
+    L = 32
+    nA, nB = inputs.droplet(L, L, L, R=5.0)
+    n = np.stack([nA, nB])
+    com, rich = O.excess_com(n, (L, L, L))
+    assert rich == 0 and np.abs(com - L // 2).max() < 1e-8
+    n2 = np.roll(n, shift=(1, -1, 2), axis=(1, 2, 3))
+    com2, _ = O.excess_com(n2, (L, L, L))
+    assert np.abs(com2 - (L // 2 + np.array([2, -1, 1]))).max() < 1e-7
+    com3, rich3 = O.excess_com(np.stack([nB, nA]), (L, L, L))
+    assert rich3 == 1 and np.abs(com3 - L // 2).max() < 1e-8
