@@ -93,7 +93,10 @@ typedef enum {
                                      pulls and stores n_J and the momentum,
                                      the second collides from those moments
                                      without pulling again (every lattice,
-                                     stencil and storage) */
+                                     stencil and storage); with a nonzero
+                                     tile (D3Q19, FP32/FP16/BF16) the second
+                                     pass stages the stencil's concentrations
+                                     in LDS (64 x 8 columns, z-chunks of 8) */
 } scmc_kernel;
 typedef enum {
     SCMC_ROUND_NEAREST = 0,   /* FP16 / BF16 offsets rounded to nearest even */

@@ -284,6 +284,11 @@ StepKey key_of(const scmc_problem &p) {
     }
     k.mom = p.tau[0] == 1.0 && (p.kernel == SCMC_KERNEL_TWO_PASS_MOM ||
                                 p.kernel == SCMC_KERNEL_AUTO);
+    // TWO_PASS_MOM with a tile asks for the LDS-staged collision pass (its
+    // shape is fixed at 64 x 8 columns and z-chunks of 8)
+    if (p.kernel == SCMC_KERNEL_TWO_PASS_MOM && p.tile[0] != 0 && p.lattice == SCMC_D3Q19 &&
+        p.storage != SCMC_F64)
+        k.mom = 2;
     k.big = (double)lattice_q(p.lattice) * p.nx * p.ny * p.nz * storage_bytes(p.storage) >=
             2147483648.0;
     return k;
@@ -320,7 +325,10 @@ int choose_kernel(const scmc_problem &p, const StepKey &k, int *kernel,
         (p.kernel == SCMC_KERNEL_AUTO && k.mom && t[0] == 0) ||
         (p.kernel == SCMC_KERNEL_AUTO && p.rounding == SCMC_ROUND_STOCHASTIC)) {
         *kernel = SCMC_KERNEL_TWO_PASS;
-        tile[0] = tile[1] = tile[2] = 0;
+        const bool lds = k.mom == 2;
+        tile[0] = lds ? 64 : 0;
+        tile[1] = lds ? 8 : 0;
+        tile[2] = lds ? 8 : 0;
         return SCMC_OK;
     }
     if (t[0] == 0) {  // default fused tile (fits every compiled design)
@@ -1368,8 +1376,11 @@ std::vector<Candidate> candidates(const scmc_problem &p, const StepKey &k0, int 
     }
     std::vector<Candidate> out;
     if (p.rounding == SCMC_ROUND_STOCHASTIC) {  // two-pass designs only
-        if (p.kernel == SCMC_KERNEL_AUTO && tau1)
+        if (p.kernel == SCMC_KERNEL_AUTO && tau1) {
             out.push_back(Candidate{SCMC_KERNEL_TWO_PASS, 0, 1, {0, 0, 0}});
+            if (k0.dim == 3 && !k0.big)
+                out.push_back(Candidate{SCMC_KERNEL_TWO_PASS, 0, 2, {64, 8, 8}});
+        }
         return out;
     }
     for (int variant : variants)
@@ -1382,8 +1393,11 @@ std::vector<Candidate> candidates(const scmc_problem &p, const StepKey &k0, int 
                 if (fused_supported(k, c.tile)) out.push_back(c);
             }
         }
-    if (p.kernel == SCMC_KERNEL_AUTO && tau1)
+    if (p.kernel == SCMC_KERNEL_AUTO && tau1) {
         out.push_back(Candidate{SCMC_KERNEL_TWO_PASS, 0, 1, {0, 0, 0}});
+        if (k0.dim == 3 && !k0.big && p.storage != SCMC_F64)  // LDS-staged collision pass
+            out.push_back(Candidate{SCMC_KERNEL_TWO_PASS, 0, 2, {64, 8, 8}});
+    }
     return out;
 }
 

@@ -43,7 +43,8 @@ struct StepKey {
     int repull = 0;  // fused design: 0 = register ring, 1 = re-pull at collide,
                   // 2 = register ring with loads issued one plane ahead,
                   // 3 / 4 = moment ring (tau = 1), plain / loads ahead
-    int mom = 0;     // two-pass design: 1 = moment passes (tau = 1)
+    int mom = 0;     // two-pass design: 1 = moment passes (tau = 1), 2 = the
+                     // same with the collision pass's pairs staged in LDS
     int big = 0;     // 1 when a component's Q planes exceed 2^31 bytes: no
                      // 32-bit buffer offsets (fused designs unavailable)
 };

@@ -19,6 +19,7 @@
 // 4Q reads + 2Q writes.
 #include <type_traits>
 
+#include "fused_impl.h"  // FusedGeom, lds_force, halo_pos, xcd_remap
 #include "site_ops.h"
 
 namespace scmc {
@@ -230,6 +231,69 @@ __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopB
     });
 }
 
+// Second pass with the stencil's concentration pairs staged in LDS: a
+// workgroup marches a TX x TY column through a z-chunk of ZC planes, keeping
+// a ring of 2 ZR + 2 pair planes (tile + halo, 8 B per node, coalesced), so
+// every pair is fetched about once per chunk instead of once per stencil
+// neighbour; the node's momentum and remainders are read directly.
+template <int TX, int TY, int ZC, int ORDER, class ST, int PSI>
+__global__ void __launch_bounds__(TX *TY)
+    k_collide_mom_lds(Member m, const typename ST::T *__restrict__ src,
+                      typename ST::T *__restrict__ dst,
+                      const typename ST::R *__restrict__ mom) {
+    using R = typename ST::R;
+    using T = typename ST::T;
+    using G = FusedGeom<ORDER>;
+    constexpr int HR = G::HR, ZR = G::ZR, NSLOT = G::NSLOT, NT = TX * TY;
+    __shared__ float2 lds[NSLOT][TY + 2 * HR][TX + 2 * HR];
+    const int ntx = (m.nx + TX - 1) / TX, nty = (m.ny + TY - 1) / TY;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int x0 = (t % ntx) * TX, y0 = ((t / ntx) % nty) * TY;
+    const int z0 = (t / (ntx * nty)) * ZC;
+    const int len = min(ZC, m.nz - z0);
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const int wx = min(TX, m.nx - x0), wy = min(TY, m.ny - y0);
+    const bool active = tx < wx && ty < wy;
+    const int nhalo = 2 * HR * (wx + 2 * HR) + wy * 2 * HR;
+    const R *base = mom + m.dens_off;
+    const float2 *pairs = reinterpret_cast<const float2 *>(base);
+    const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
+    const int nxy = m.nx * m.ny;
+    for (int k = 0; k < len + 2 * ZR; ++k) {
+        const int zl = wrap1(z0 - ZR + k, m.nz);
+        auto &plane = lds[k % NSLOT];
+        if (active) plane[ty + HR][tx + HR] = pairs[zl * nxy + (y0 + ty) * m.nx + x0 + tx];
+        for (int h = tid; h < nhalo; h += NT) {
+            int lx, ly;
+            halo_pos<HR>(h, wx, wy, lx, ly);
+            plane[ly][lx] = pairs[zl * nxy + wrap1(y0 - HR + ly, m.ny) * m.nx +
+                                  wrap1(x0 - HR + lx, m.nx)];
+        }
+        __syncthreads();
+        if (k >= 2 * ZR && active) {
+            const int zc = wrap1(z0 + k - 2 * ZR, m.nz);
+            const int s = zc * nxy + (y0 + ty) * m.nx + x0 + tx;
+            R mm[NMOM], FA[3], FB[3];
+            lds_force<TX, TY, ORDER, R, PSI>(m, lds, k, tx, ty, mm[0], mm[1], FA, FB);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) mm[2 + c] = base[(2 + c) * (long)m.N + s];
+            unpack_rem<R>(reinterpret_cast<const unsigned *>(base + 5 * (long)m.N)[s], mm);
+            const int voff = s * (int)sizeof(T);
+            if (m.sr) {
+                SiteRng rng(m.seed, *m.step_ctr, (unsigned)(m.pop_off + s));
+                collide_tau1<3, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
+                    RawBuf<T>::store_nt(ST::to_raw_sr(v, ref, rng.next()), db.r[J], voff,
+                                        i * db.plane_bytes);
+                });
+            } else {
+                collide_tau1<3, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
+                    RawBuf<T>::store_nt(ST::to_raw(v, ref), db.r[J], voff, i * db.plane_bytes);
+                });
+            }
+        }
+    }
+}
+
 template <class ST>
 __global__ void __launch_bounds__(256)
     k_moments_buf(Member m, const typename ST::T *__restrict__ src,
@@ -427,13 +491,20 @@ static dim3 tp_grid(const Member &m) {
     return dim3((m.nx + TP_BX - 1) / TP_BX, (m.ny + TP_BY - 1) / TP_BY, m.nz);
 }
 
-// Blocks of the buffer-form moment passes (measured on 128^3): one 64-wide row
-// per block for the pull pass, 128 x 2 for the collision pass when rows are
-// long enough.
-static void mom_blocks(const Member &m, dim3 *gm, dim3 *bm, dim3 *gc, dim3 *bc) {
+// Launch shapes of the buffer-form moment passes (measured on 128^3): one
+// 64-wide row per block for the pull pass; the LDS-staged collision pass
+// (StepKey::mom == 2) marches 64 x 8 columns through z-chunks of 8 planes.
+constexpr int CL_TX = 64, CL_TY = 8, CL_ZC = 8;
+
+static void mom_blocks(const Member &m, bool lds, dim3 *gm, dim3 *bm, dim3 *gc,
+                       dim3 *bc) {
     *bm = dim3(64, 1, 1);
     *gm = dim3((m.nx + 63) / 64, m.ny, m.nz);
-    if (m.nx >= 128) {
+    if (lds) {
+        const int ntx = (m.nx + CL_TX - 1) / CL_TX, nty = (m.ny + CL_TY - 1) / CL_TY;
+        *bc = dim3(CL_TX, CL_TY, 1);
+        *gc = dim3(ntx * nty * ((m.nz + CL_ZC - 1) / CL_ZC), 1, 1);
+    } else if (m.nx >= 128) {  // direct gathers: 128 x 2 blocks on long rows
         *bc = dim3(128, 2, 1);
         *gc = dim3((m.nx + 127) / 128, (m.ny + 1) / 2, m.nz);
     } else {
@@ -458,11 +529,16 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
             if constexpr (buf_form<D, ST>()) {
                 if (k.mom && !k.big) {
                     dim3 gm, bm, gc, bc;
-                    mom_blocks(m, &gm, &bm, &gc, &bc);
+                    mom_blocks(m, k.mom == 2, &gm, &bm, &gc, &bc);
                     hipLaunchKernelGGL((k_moments_buf<ST>), gm, bm, 0, st, m,
                                        (const T *)src, (R *)dens);
-                    hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P>), gc, bc, 0, st, m,
-                                       (const T *)src, (T *)dst, (const R *)dens);
+                    if (k.mom == 2)
+                        hipLaunchKernelGGL((k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P>),
+                                           gc, bc, 0, st, m, (const T *)src, (T *)dst,
+                                           (const R *)dens);
+                    else
+                        hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P>), gc, bc, 0, st, m,
+                                           (const T *)src, (T *)dst, (const R *)dens);
                     done = true;
                 }
             }
@@ -502,8 +578,10 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dn, NodeLaunch *sn,
             if constexpr (buf_form<D, ST>()) {
                 if (k.mom && !k.big) {
                     dn->func = (void *)&k_moments_buf<ST>;
-                    sn->func = (void *)&k_collide_mom_buf<O, ST, P>;
-                    mom_blocks(m, &dn->grid, &dn->block, &sn->grid, &sn->block);
+                    sn->func = k.mom == 2
+                                   ? (void *)&k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P>
+                                   : (void *)&k_collide_mom_buf<O, ST, P>;
+                    mom_blocks(m, k.mom == 2, &dn->grid, &dn->block, &sn->grid, &sn->block);
                 }
             }
             ok = true;

@@ -303,7 +303,8 @@ def test_full_size_sampled_single_step():
     (scmc.KERNEL_FUSED_PIPE, (32, 8, 16)), (scmc.KERNEL_FUSED_PIPE, (64, 8, 8)),
     (scmc.KERNEL_FUSED_MOM, (64, 8, 16)), (scmc.KERNEL_FUSED_MOM, (128, 8, 8)),
     (scmc.KERNEL_FUSED_MOM, (64, 16, 32)), (scmc.KERNEL_FUSED_MOM, (32, 8, 8)),
-    (scmc.KERNEL_FUSED_MOM_PIPE, (32, 8, 16)), (scmc.KERNEL_FUSED_MOM_PIPE, (64, 8, 8))])
+    (scmc.KERNEL_FUSED_MOM_PIPE, (32, 8, 16)), (scmc.KERNEL_FUSED_MOM_PIPE, (64, 8, 8)),
+    (scmc.KERNEL_TWO_PASS_MOM, (64, 8, 8))])
 @pytest.mark.parametrize("stencil", [scmc.E4, scmc.E6])
 def test_fused_designs_match_two_pass(kernel, tile, stencil):
     """Every fused design and tile (ragged x, y and z chunks included) gives
@@ -320,7 +321,7 @@ def test_fused_designs_match_two_pass(kernel, tile, stencil):
     fr, _ = ref.scmc_get_populations()
     s = scmc.Sim(scmc.problem(scmc.D3Q19, stencil, shape, g=g, storage=scmc.F32,
                               kernel=kernel, tile=tile))
-    assert s.scmc_config() == (kernel, tile)
+    assert s.scmc_config() == (kernel, tile)   # TWO_PASS_MOM + tile: LDS-staged pass 2
     s.scmc_set_density(nA, nB)
     s.scmc_step(12)
     f, _ = s.scmc_get_populations()
