@@ -1,0 +1,70 @@
+"""The paper's own parameter set (Sec. 4) on the GPU library: psi =
+exp(-1/n) self-interactions with G_JJ from eq. self_p (G_c c_s^2 = -e^2/3,
+dG_c = 0.4, dG_AB = 0), G c_s^2 = 0.5, D3Q19 with the E4 stencil, odd boxes
+and droplets of radius L/4 between the bulk values of a converged flat
+interface (127 x 5 x 5), run until Delta P changes by less than 1e-5 over
+2^11 steps.
+
+In the symmetric case the Tolman length vanishes (Sec. 4, Fig. 4a), so
+sigma(R_s)/sigma_0 - 1 carries no 1/R_s term: going from L = 31 to L = 63
+(R_s ~ 8 to ~16) divides it by about (16/8)^2 = 4, and A-rich and B-rich
+droplets are mirror images.  These are physics checks of the library on the
+paper's set-up; the oracle parity of the same operators is tested elsewhere.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2112_02574_amd import inputs
+from paper_2112_02574_amd import scmc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _couplings(dGAB, dGc=0.4):
+    Gc = -math.e ** 2 / 3.0           # critical G c_s^2 of psi = exp(-1/n)
+    gAA = Gc * (1 - dGc * (1 + dGAB))  # eq. self_p
+    gBB = Gc * (1 - dGc)
+    return ((gAA, 0.5), (0.5, gBB))
+
+
+def test_symmetric_paper_set_has_no_tolman_term():
+    g = _couplings(0.0)
+    psi = scmc.PSI_EXP_NEG_INV
+    pf = scmc.problem(scmc.D3Q19, scmc.E4, (31, 31, 31), g=g, psi_self=psi, storage=scmc.F64)
+    bulk, _ = scmc.scmc_flat_equilibrium(pf, lx=127, guess=(2.0, 0.05, 0.05, 2.0), tol=1e-11,
+                                         max_steps=400000)
+    assert bulk[0] - bulk[2] > 1.5 and abs(bulk[0] - bulk[3]) < 1e-3   # two mirror phases
+    # flat sigma_0 on the strip between those bulks
+    fl = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E4, (5, 5, 127), g=g, psi_self=psi,
+                               storage=scmc.F64))
+    x = np.arange(127)
+    inside = (x >= 31) & (x < 95)
+    fl.scmc_set_density(np.broadcast_to(np.where(inside, bulk[0], bulk[2]), (5, 5, 127)).copy(),
+                        np.broadcast_to(np.where(inside, bulk[1], bulk[3]), (5, 5, 127)).copy())
+    fl.scmc_step(100000)
+    sigma0 = fl.scmc_observables(scmc.OBS_FLAT)["sigma0"]
+    fl.close()
+    excess = {}
+    for L in (31, 63):
+        res = []
+        for a_rich in (True, False):
+            s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E4, (L, L, L), g=g, psi_self=psi,
+                                      storage=scmc.F32))
+            s.scmc_set_density(*inputs.droplet(L, L, L, R=L / 4, a_rich=a_rich, bulk=bulk))
+            c = s.scmc_run_to_convergence(L / 4, dt=2048, max_steps=200000, tol_dP=1e-5)
+            o = s.scmc_observables(scmc.OBS_DROPLET, L / 4)
+            s.close()
+            print(f"L {L} a_rich {a_rich}: steps {c['step']} dP {o['dP']:.6g} R_s {o['R_s']:.5f} "
+                  f"sigma_s/sigma0 {o['sigma_s'] / sigma0:.4f}", flush=True)
+            assert c["converged"]
+            res.append(o)
+        assert abs(res[0]["dP"] - res[1]["dP"]) < 1e-4 * res[0]["dP"]
+        assert abs(res[0]["R_s"] - res[1]["R_s"]) < 1e-3 * res[0]["R_s"]
+        excess[L] = res[0]["sigma_s"] / sigma0 - 1.0
+        assert res[0]["R_s"] == pytest.approx(L / 4, rel=0.05)
+    ratio = excess[31] / excess[63]
+    assert 3.5 < ratio < 4.5, ratio
