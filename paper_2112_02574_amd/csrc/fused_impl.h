@@ -58,31 +58,37 @@ __device__ __forceinline__ void lds_force(
     const float2 own = lds[(k - ZR) % G::NSLOT][ty + HR][tx + HR];
     nA = own.x;
     nB = own.y;
-    R cA[3] = {0, 0, 0}, cB[3] = {0, 0, 0}, sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0};
+    // pairs (e, -e) summed in FP64, as in site_force_fn
+    static_assert(Sten::point_symmetric(), "stencil table must list e and -e mirrored");
+    double cA[3] = {0, 0, 0}, cB[3] = {0, 0, 0}, sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0};
     const bool selfA = m.self_on & 1, selfB = m.self_on & 2;
 #pragma unroll
-    for (int a = 0; a < Sten::NE; ++a) {
+    for (int a = Sten::NE / 2; a < Sten::NE; ++a) {
         constexpr auto T = Sten::T;
         const int ex = T.e[a][0], ey = T.e[a][1], ez = T.e[a][2];
-        const float2 d = lds[(k - ZR + ez) % G::NSLOT][ty + HR + ey][tx + HR + ex];
-        const R nAt = d.x, nBt = d.y;
+        const float2 p = lds[(k - ZR + ez) % G::NSLOT][ty + HR + ey][tx + HR + ex];
+        const float2 q = lds[(k - ZR - ez) % G::NSLOT][ty + HR - ey][tx + HR - ex];
+        const R pAt = p.x, pBt = p.y, mAt = q.x, mBt = q.y;
+        const R dA = pAt - mAt, dB = pBt - mBt;
         const R W = (R)T.W[a];
         const int e3[3] = {ex, ey, ez};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (e3[c] == 0) continue;
-            const R We = W * (R)e3[c];
-            cA[c] += We * nBt;
-            cB[c] += We * nAt;
+            const double We = (double)(W * (R)e3[c]);
+            cA[c] += We * (double)dB;
+            cB[c] += We * (double)dA;
         }
-        if (selfA || selfB) {
-            const R pA = psi_of<R, PSI>(nAt), pB = psi_of<R, PSI>(nBt);
+        // with psi = n the self sums equal the cross sums (sA = cB, sB = cA)
+        if (PSI != 0 && (selfA || selfB)) {
+            const R qA = psi_of<R, PSI>(pAt) - psi_of<R, PSI>(mAt);
+            const R qB = psi_of<R, PSI>(pBt) - psi_of<R, PSI>(mBt);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (e3[c] == 0) continue;
-                const R We = W * (R)e3[c];
-                sA[c] += We * pA;
-                sB[c] += We * pB;
+                const double We = (double)(W * (R)e3[c]);
+                sA[c] += We * (double)qA;
+                sB[c] += We * (double)qB;
             }
         }
     }
@@ -92,8 +98,9 @@ __device__ __forceinline__ void lds_force(
     const R pB = selfB ? psi_of<R, PSI>(nB) : R(0);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        FA[c] = -gAB * nA * cA[c] - gAA * pA * sA[c];
-        FB[c] = -gBA * nB * cB[c] - gBB * pB * sB[c];
+        const R tA = (R)(PSI == 0 ? cB[c] : sA[c]), tB = (R)(PSI == 0 ? cA[c] : sB[c]);
+        FA[c] = -gAB * nA * (R)cA[c] - gAA * pA * tA;
+        FB[c] = -gBA * nB * (R)cB[c] - gBB * pB * tB;
     }
 }
 

@@ -121,6 +121,14 @@ template <int D, int ORDER> struct Stencil {
         return t;
     }
     static constexpr Table T = make();
+    // the table runs lexicographically over (z, y, x), so entry NE - 1 - a is
+    // the opposite of entry a with the same weight
+    static constexpr bool point_symmetric() {
+        for (int a = 0; a < NE; ++a)
+            for (int k = 0; k < 3; ++k)
+                if (T.e[NE - 1 - a][k] != -T.e[a][k] || T.W[NE - 1 - a] != T.W[a]) return false;
+        return NE % 2 == 0;
+    }
 };
 
 // ----------------------------------------------------------- storage formats

@@ -72,57 +72,72 @@ __device__ __forceinline__ void pull_site(
     }
 }
 
+// Order-free sums.  Every sum over populations or stencil neighbours is
+// accumulated in FP64: a handful of FP32 values, or products of two FP32
+// values, add up exactly there, so the result does not depend on the order of
+// the terms.  A mirror reflection of the lattice only permutes those terms
+// (and flips signs, which round symmetrically), so with FP32 storage the step
+// commutes bit for bit with the reflections: a droplet centred on a node
+// keeps its centre, which the convergence gate of Sec. 4 checks to 1e-3,
+// instead of being pushed by the same rounding bias every step.
 template <int D, class R>
 __device__ __forceinline__ void site_density(const R (&f)[2][Lattice<D>::Q],
                                              R &nA, R &nB) {
-    R a = 0, b = 0;
+    double a = 0, b = 0;
 #pragma unroll
     for (int i = 0; i < Lattice<D>::Q; ++i) {
-        a += f[0][i];
-        b += f[1][i];
+        a += (double)f[0][i];
+        b += (double)f[1][i];
     }
-    nA = a;
-    nB = b;
+    nA = (R)a;
+    nB = (R)b;
 }
 
 // Stencil sums of eq. sc_force around site (x, y, z), with the stencil
 // concentrations returned by fetch(t, n_A, n_B) (t = linear site index), then
-// the force on both components.
+// the force on both components.  The stencil is point-symmetric, so the sum
+// runs over pairs (e, -e): W e (Phi(x + e) - Phi(x - e)).  The difference is
+// exactly odd under e -> -e and the pair sums are accumulated in FP64 (the
+// order-free sums above).
 template <int D, int ORDER, int PSI, class R, class Fetch>
 __device__ __forceinline__ void site_force_fn(const Member &m, int x, int y, int z,
                                               R nA, R nB, R (&FA)[3], R (&FB)[3],
                                               Fetch &&fetch) {
     using S = Stencil<D, ORDER>;
-    R cA[3] = {0, 0, 0}, cB[3] = {0, 0, 0};
-    R sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0};
+    static_assert(S::point_symmetric(), "stencil table must list e and -e mirrored");
+    double cA[3] = {0, 0, 0}, cB[3] = {0, 0, 0};
+    double sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0};
     const bool selfA = m.self_on & 1, selfB = m.self_on & 2;
 #pragma unroll
-    for (int a = 0; a < S::NE; ++a) {
+    for (int a = S::NE / 2; a < S::NE; ++a) {
         constexpr auto T = S::T;
         const int ex = T.e[a][0], ey = T.e[a][1], ez = T.e[a][2];
-        const int xs = wrap1(x + ex, m.nx);
-        const int ys = wrap1(y + ey, m.ny);
-        const int zs = D == 3 ? wrap1(z + ez, m.nz) : 0;
-        const int t = (zs * m.ny + ys) * m.nx + xs;  // N < 2^31 (validated)
-        R nAt, nBt;
-        fetch(t, nAt, nBt);
+        const int zp = D == 3 ? wrap1(z + ez, m.nz) : 0, zm = D == 3 ? wrap1(z - ez, m.nz) : 0;
+        const int tp = (zp * m.ny + wrap1(y + ey, m.ny)) * m.nx + wrap1(x + ex, m.nx);
+        const int tm = (zm * m.ny + wrap1(y - ey, m.ny)) * m.nx + wrap1(x - ex, m.nx);
+        R pAt, pBt, mAt, mBt;  // N < 2^31 (validated)
+        fetch(tp, pAt, pBt);
+        fetch(tm, mAt, mBt);
+        const R dA = pAt - mAt, dB = pBt - mBt;
         const R W = (R)T.W[a];
         const int e3[3] = {ex, ey, ez};
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             if (e3[k] == 0) continue;
-            const R We = W * (R)e3[k];
-            cA[k] += We * nBt;
-            cB[k] += We * nAt;
+            const double We = (double)(W * (R)e3[k]);
+            cA[k] += We * (double)dB;
+            cB[k] += We * (double)dA;
         }
-        if (selfA || selfB) {
-            const R pA = psi_of<R, PSI>(nAt), pB = psi_of<R, PSI>(nBt);
+        // with psi = n the self sums equal the cross sums (sA = cB, sB = cA)
+        if (PSI != 0 && (selfA || selfB)) {
+            const R qA = psi_of<R, PSI>(pAt) - psi_of<R, PSI>(mAt);
+            const R qB = psi_of<R, PSI>(pBt) - psi_of<R, PSI>(mBt);
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 if (e3[k] == 0) continue;
-                const R We = W * (R)e3[k];
-                sA[k] += We * pA;
-                sB[k] += We * pB;
+                const double We = (double)(W * (R)e3[k]);
+                sA[k] += We * (double)qA;
+                sB[k] += We * (double)qB;
             }
         }
     }
@@ -132,8 +147,9 @@ __device__ __forceinline__ void site_force_fn(const Member &m, int x, int y, int
     const R pB = selfB ? psi_of<R, PSI>(nB) : R(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        FA[k] = -gAB * nA * cA[k] - gAA * pA * sA[k];
-        FB[k] = -gBA * nB * cB[k] - gBB * pB * sB[k];
+        const R tA = (R)(PSI == 0 ? cB[k] : sA[k]), tB = (R)(PSI == 0 ? cA[k] : sB[k]);
+        FA[k] = -gAB * nA * (R)cA[k] - gAA * pA * tA;
+        FB[k] = -gBA * nB * (R)cB[k] - gBB * pB * tB;
     }
 }
 
@@ -159,41 +175,56 @@ __device__ __forceinline__ void site_collide(const Member &m,
                                              R nA, R nB, const R (&FA)[3],
                                              const R (&FB)[3], Sink &&sink) {
     using L = Lattice<D>;
-    R mx = 0, my = 0, mz = 0;
+    double mx = 0, my = 0, mz = 0;  // order-free sums (see site_density)
 #pragma unroll
     for (int J = 0; J < 2; ++J)
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            if (L::CX[i]) mx += (R)L::CX[i] * f[J][i];
-            if (L::CY[i]) my += (R)L::CY[i] * f[J][i];
-            if (D == 3 && L::CZ[i]) mz += (R)L::CZ[i] * f[J][i];
+            if (L::CX[i]) mx += (double)L::CX[i] * (double)f[J][i];
+            if (L::CY[i]) my += (double)L::CY[i] * (double)f[J][i];
+            if (D == 3 && L::CZ[i]) mz += (double)L::CZ[i] * (double)f[J][i];
         }
     const R inv = R(1) / (nA + nB);
-    const R ux = (mx + R(0.5) * (FA[0] + FB[0])) * inv;
-    const R uy = (my + R(0.5) * (FA[1] + FB[1])) * inv;
-    const R uz = D == 3 ? (mz + R(0.5) * (FA[2] + FB[2])) * inv : R(0);
+    const R ux = ((R)mx + R(0.5) * (FA[0] + FB[0])) * inv;
+    const R uy = ((R)my + R(0.5) * (FA[1] + FB[1])) * inv;
+    const R uz = D == 3 ? ((R)mz + R(0.5) * (FA[2] + FB[2])) * inv : R(0);
     const R uu = ux * ux + uy * uy + uz * uz;
-    const R omega = (R)m.omega, cf = R(1) - R(0.5) * omega;
+    const R omega = (R)m.omega, keep = R(1) - omega, cf = R(1) - R(0.5) * omega;
     const R n0[2] = {(R)m.n0[0], (R)m.n0[1]};
+    constexpr Opposite<D> OP = Opposite<D>::make();
+    // Velocities xi and -xi are collided together: with t = omega n_J xi.u,
+    //   E = w [a_J + 9/2 (xi.u) (t + 2 c_f xi.F_J)],  O = w [3 t + 3 c_f xi.F_J],
+    //   a_J = omega n_J (1 - 3/2 u.u) - 3 c_f u.F_J,  c_f = 1 - omega / 2,
+    // f*_xi = (1 - omega) f_xi + (E + O) and f*_-xi = (1 - omega) f_-xi + (E - O)
+    // (eq. lbm with the Guo source).  Every velocity pair then runs the same
+    // operations on sign-flipped operands, which keeps the step exactly
+    // covariant under mirror reflections (see site_density).
 #pragma unroll
     for (int J = 0; J < 2; ++J) {
         const R *F = J == 0 ? FA : FB;
         const R nJ = J == 0 ? nA : nB;
         const R uF = ux * F[0] + uy * F[1] + uz * F[2];
+        const R on = omega * nJ;
+        const R a = on * (R(1) - R(1.5) * uu) - R(3) * cf * uF;
         double moving = 0, nJx = (double)f[J][0];
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
-            const R cx = (R)L::CX[i], cy = (R)L::CY[i], cz = (R)L::CZ[i];
-            const R xu = cx * ux + cy * uy + cz * uz;
-            const R xF = cx * F[0] + cy * F[1] + cz * F[2];
+            const int ib = OP.opp[i];
+            if (ib < i) continue;
+            R xu = 0, xF = 0;
+            if (L::CX[i]) { xu += (R)L::CX[i] * ux; xF += (R)L::CX[i] * F[0]; }
+            if (L::CY[i]) { xu += (R)L::CY[i] * uy; xF += (R)L::CY[i] * F[1]; }
+            if (D == 3 && L::CZ[i]) { xu += (R)L::CZ[i] * uz; xF += (R)L::CZ[i] * F[2]; }
             const R w = (R)L::W[i];
-            const R feq = nJ * w *
-                          (R(1) + R(3) * xu + R(4.5) * xu * xu - R(1.5) * uu);
-            const R S = w * (R(3) * xF + R(9) * xu * xF - R(3) * uF);
-            const R out = f[J][i] - omega * (f[J][i] - feq) + cf * S;
-            sink(J, i, out, w * n0[J]);
-            moving += (double)out;
-            nJx += (double)f[J][i];
+            const R t = on * xu, cF = cf * xF;
+            const R E = w * (a + R(4.5) * xu * (t + R(2) * cF));
+            const R O = w * (R(3) * t + R(3) * cF);
+            const R fp = keep * f[J][i] + (E + O);
+            const R fm = keep * f[J][ib] + (E - O);
+            sink(J, i, fp, w * n0[J]);
+            sink(J, ib, fm, w * n0[J]);
+            moving += (double)fp + (double)fm;
+            nJx += (double)f[J][i] + (double)f[J][ib];
         }
         // rest population from the mass balance sum_i f*_i = sum_i f_i (BGK
         // and the Guo source conserve mass), both sums exact in FP64: rounded
@@ -216,21 +247,21 @@ __device__ __forceinline__ void site_moments(const R (&f)[2][Lattice<D>::Q],
                                              R (&mom)[NMOM]) {
     using L = Lattice<D>;
     double nA = 0, nB = 0;
-    R jx = 0, jy = 0, jz = 0;
+    double jx = 0, jy = 0, jz = 0;  // order-free sums (see site_density)
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         nA += (double)f[0][i];
         nB += (double)f[1][i];
-        const R t = f[0][i] + f[1][i];
-        if (L::CX[i]) jx += (R)L::CX[i] * t;
-        if (L::CY[i]) jy += (R)L::CY[i] * t;
-        if (D == 3 && L::CZ[i]) jz += (R)L::CZ[i] * t;
+        const double t = (double)f[0][i] + (double)f[1][i];
+        if (L::CX[i]) jx += (double)L::CX[i] * t;
+        if (L::CY[i]) jy += (double)L::CY[i] * t;
+        if (D == 3 && L::CZ[i]) jz += (double)L::CZ[i] * t;
     }
     mom[0] = (R)nA;
     mom[1] = (R)nB;
-    mom[2] = jx;
-    mom[3] = jy;
-    mom[4] = jz;
+    mom[2] = (R)jx;
+    mom[3] = (R)jy;
+    mom[4] = (R)jz;
     mom[5] = (R)(nA - (double)mom[0]);
     mom[6] = (R)(nB - (double)mom[1]);
 }

@@ -1,0 +1,75 @@
+"""Mirror symmetry of the FP32 / FP16 step, bit for bit.
+
+The lattice Boltzmann step of eq. lbm with the force of eq. sc_force commutes
+with the reflections x -> 2c - x of each axis (the velocity sets and the
+stencils are closed under them).  A droplet centred on the node c therefore
+stays exactly mirror-symmetric and its centre of mass stays at c, which is
+what the convergence gate of Sec. 4 (centre within 1e-3) relies on.
+
+The library makes every sum order-free (FP64 accumulation of FP32 values,
+pairs of opposite stencil vectors and of opposite velocities), so the stored
+fields after hundreds of steps must equal their mirror images exactly, in
+every step design.  Before those sums were order-free, FP32 rounding pushed
+the droplet by the same amount every step and the centre drifted by 0.06
+(L = 31) to 0.3 (L = 63) lattice units before convergence.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2112_02574_amd import inputs
+from paper_2112_02574_amd import scmc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GC = -math.e ** 2 / 3.0
+# the paper's parameter set (psi = exp(-1/n), E4, dG_AB = 0, odd L) and the
+# 128^3 benchmark's (psi = n, E6, g_AB = 1.8) on a small even box
+CASES = {
+    "paper_E4_L31": (scmc.E4, ((GC * 0.6, 0.5), (0.5, GC * 0.6)), scmc.PSI_EXP_NEG_INV, 31,
+                     (2.072258, 0.037026, 0.037024, 2.072272)),
+    "bench_E6_L32": (scmc.E6, ((0.0, 1.8), (1.8, 0.0)), scmc.PSI_N, 32,
+                     (1.059549270199, -0.001218167868, -0.001218167868, 1.059549270199)),
+}
+DESIGNS = {
+    "auto": (scmc.KERNEL_AUTO, (0, 0, 0)),
+    "two_pass": (scmc.KERNEL_TWO_PASS, (0, 0, 0)),
+    "two_pass_mom_lds": (scmc.KERNEL_TWO_PASS_MOM, (64, 8, 8)),
+    "fused": (scmc.KERNEL_FUSED, (64, 4, 16)),
+    "fused_mom": (scmc.KERNEL_FUSED_MOM, (64, 4, 16)),
+}
+
+
+def _mirror_defect(n):
+    """max |n - n reflected about c = L // 2| over the three axes of (J, z, y, x)."""
+    worst = 0.0
+    for ax in (1, 2, 3):
+        L = n.shape[ax]
+        idx = (2 * (L // 2) - np.arange(L)) % L
+        worst = max(worst, float(np.abs(n - np.take(n, idx, axis=ax)).max()))
+    return worst
+
+
+@pytest.mark.parametrize("storage", [scmc.F32, scmc.F16_OFF])
+@pytest.mark.parametrize("design", list(DESIGNS))
+@pytest.mark.parametrize("case", list(CASES))
+def test_step_commutes_with_mirror_reflections(case, design, storage):
+    stencil, g, psi, L, bulk = CASES[case]
+    kernel, tile = DESIGNS[design]
+    print(f"{case} {design} storage {storage}", flush=True)
+    n0 = (0.5 * (bulk[0] + bulk[2]), 0.5 * (bulk[1] + bulk[3]))
+    s = scmc.Sim(scmc.problem(scmc.D3Q19, stencil, (L, L, L), g=g, psi_self=psi, storage=storage,
+                              n0=n0, kernel=kernel, tile=tile))
+    s.scmc_set_density(*inputs.droplet(L, L, L, R=L / 4, bulk=bulk))
+    s.scmc_step(600)
+    n = s.scmc_get_fields()
+    c = s.scmc_convergence_check(L / 4)
+    s.close()
+    assert np.isfinite(n).all()
+    assert _mirror_defect(n) == 0.0
+    if L % 2:
+        # odd box: the cell is symmetric about c, so the excess centre is c
+        assert c["com_offset"] < 1e-12
