@@ -25,6 +25,7 @@ timed run.
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -431,6 +432,88 @@ def precision_study(args, out_md):
     print(json.dumps(out), flush=True)
 
 
+def paper_couplings(dGAB, dGc=0.4):
+    """g = G c_s^2 of the paper's runs (Sec. 4): G c_s^2 = 0.5 between the
+    components and the self couplings of eq. self_p around the critical
+    G_c c_s^2 = -e^2/3 of psi = exp(-1/n)."""
+    Gc = -math.e ** 2 / 3.0
+    return ((Gc * (1 - dGc * (1 + dGAB)), 0.5), (0.5, Gc * (1 - dGc)))
+
+
+def tolman_sweep(args, out_md):
+    """The paper's Tolman analysis at reduced size: for each dG_AB a flat
+    interface (127 x 5 x 5, FP64) gives the bulk values and sigma_0, then A-rich
+    and B-rich droplets with R0 = L/4 on odd boxes run (FP32) until Delta P
+    changes by less than 1e-5 over 2^11 steps; sigma_s = Delta P R_s / 2 at the
+    signed curvature +-1/R_s goes into the fit of eq. sigma_c."""
+    import torch  # noqa: F401  (loads the HIP runtime before the library)
+    from paper_2112_02574_amd import inputs, scmc
+    dgs = [float(v) for v in args.tolman_dg.split(",")]
+    Ls = [int(v) for v in args.tolman_L.split(",")]
+    psi = scmc.PSI_EXP_NEG_INV
+    lines = ["# Tolman length on the paper's parameter set (psi = exp(-1/n), D3Q19 / E4)", "",
+             "Command (repository root, one MI355X):", "",
+             f"    python3 bench.py --tolman OUT_MD --tolman-dg {args.tolman_dg} --tolman-L {args.tolman_L}",
+             "", "| dG_AB | L | droplet | steps | centre offset | Delta P | R_s | sigma_s / sigma_0 |",
+             "|---|---|---|---|---|---|---|---|"]
+    fits = []
+    for dg in dgs:
+        g = paper_couplings(dg)
+        t0 = time.time()
+        pf = scmc.problem(scmc.D3Q19, scmc.E4, (31, 31, 31), g=g, psi_self=psi, storage=scmc.F64)
+        bulk, _ = scmc.scmc_flat_equilibrium(pf, lx=127, guess=(2.0, 0.05, 0.05, 2.0), tol=1e-11,
+                                             max_steps=400000)
+        fl = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E4, (5, 5, 127), g=g, psi_self=psi,
+                                   storage=scmc.F64))
+        x = np.arange(127)
+        inside = (x >= 31) & (x < 95)
+        fl.scmc_set_density(np.broadcast_to(np.where(inside, bulk[0], bulk[2]), (5, 5, 127)).copy(),
+                            np.broadcast_to(np.where(inside, bulk[1], bulk[3]), (5, 5, 127)).copy())
+        fl.scmc_step(100000)
+        sigma0 = fl.scmc_observables(scmc.OBS_FLAT)["sigma0"]
+        fl.close()
+        print(f"dG_AB {dg}: bulk {np.round(bulk, 6).tolist()} sigma0 {sigma0:.6f} "
+              f"({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+        curv, sig = [], []
+        for L in Ls:
+            for a_rich in (True, False):
+                t0 = time.time()
+                n0 = (0.5 * (bulk[0] + bulk[2]), 0.5 * (bulk[1] + bulk[3]))
+                s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E4, (L, L, L), g=g, psi_self=psi,
+                                          storage=scmc.F32, n0=n0))
+                s.scmc_set_density(*inputs.droplet(L, L, L, R=L / 4, a_rich=a_rich, bulk=bulk))
+                try:
+                    c = s.scmc_run_to_convergence(L / 4, dt=2048, max_steps=args.tolman_max_steps,
+                                                  tol_dP=1e-5)
+                    o = s.scmc_observables(scmc.OBS_DROPLET, L / 4)
+                except scmc.ScmcError as e:
+                    c, o = None, None
+                    print(f"  L {L} a_rich {a_rich}: {e}", file=sys.stderr, flush=True)
+                s.close()
+                kind = "A-rich" if a_rich else "B-rich"
+                if c is None or not c["converged"] or c["com_offset"] > 1e-3:
+                    lines.append(f"| {dg:+.2f} | {L} | {kind} | — | — | — | — | not converged |")
+                    continue
+                curv.append((1.0 if a_rich else -1.0) / o["R_s"])
+                sig.append(o["sigma_s"])
+                lines.append(f"| {dg:+.2f} | {L} | {kind} | {c['step']} | {c['com_offset']:.0e} | "
+                             f"{o['dP']:.6f} | {o['R_s']:.4f} | {o['sigma_s'] / sigma0:.5f} |")
+                print(f"  L {L} {kind}: steps {c['step']} R_s {o['R_s']:.4f} "
+                      f"sigma_s/sigma0 {o['sigma_s'] / sigma0:.5f} ({time.time() - t0:.1f} s)",
+                      file=sys.stderr, flush=True)
+        fit = scmc.scmc_curvature_fit(curv, sig) if len(curv) >= 3 else (float("nan"),) * 3
+        fits.append((dg, sigma0, fit, len(curv)))
+    lines += ["", "Fit of eq. sigma_c over the converged droplets (scmc_curvature_fit):", "",
+              "| dG_AB | sigma_0 flat | sigma_0 fit | relative difference | delta (lu) | 2 kbar + k (lu^2) | points |",
+              "|---|---|---|---|---|---|---|"]
+    for dg, sigma0, (s0, d, k), n in fits:
+        lines.append(f"| {dg:+.2f} | {sigma0:.6f} | {s0:.6f} | {abs(s0 / sigma0 - 1):.2e} | "
+                     f"{d:+.4f} | {k:.3f} | {n} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def _fmt(v, f):
     return f % v if v is not None else "-"
 
@@ -473,6 +556,14 @@ def main():
     ap.add_argument("--precision", metavar="OUT_MD", default=None,
                     help="only run the storage-precision study (256^3 asymmetric droplet; "
                          "use --size 256 --steps N) and write its summary to OUT_MD")
+    ap.add_argument("--tolman", metavar="OUT_MD", default=None,
+                    help="only run the Tolman-length sweep on the paper's parameter set and "
+                         "write its summary to OUT_MD")
+    ap.add_argument("--tolman-dg", default="-0.88,-0.44,0,0.44,0.88",
+                    help="comma-separated asymmetry parameters dG_AB of the sweep")
+    ap.add_argument("--tolman-L", default="31,47,63,95,127",
+                    help="comma-separated odd box sizes of the sweep (R0 = L/4)")
+    ap.add_argument("--tolman-max-steps", type=int, default=400000)
     ap.add_argument("--summarize", metavar="DIR", default=None,
                     help="only write the profiles/ summaries from rocprofv3 output in DIR")
     args = ap.parse_args()
@@ -481,6 +572,9 @@ def main():
         return
     if args.summarize:
         summarize_profiles(args.summarize, args.size)
+        return
+    if args.tolman:
+        tolman_sweep(args, args.tolman)
         return
     if args.copy_calib:
         import torch

@@ -225,6 +225,19 @@ int scmc_convergence_check(scmc_sim *s, double R0, double tol_dP, double tol_du,
  * until converged or max_steps have run; *out holds the last check. */
 int scmc_run_to_convergence(scmc_sim *s, double R0, int64_t dt, int64_t max_steps,
                             double tol_dP, double tol_du, scmc_convergence *out);
+/* (Returns SCMC_ENONFINITE as soon as a check finds Delta P not finite.) */
+
+/* Curvature expansion of the surface tension (eq. sigma_c, Sec. 4):
+ *   sigma(R_s) = sigma_0 (1 - 2 delta c + (2 kbar + k) c^2),  c = 1 / R_s,
+ * with c signed: positive for a droplet of the A-rich phase, negative for a
+ * droplet of the B-rich phase (whose A-rich surroundings curve the other
+ * way).  Host-only least-squares fit of the quadratic through n >= 3 points
+ * (curvature[i], sigma[i]), e.g. sigma[i] = Delta P R_s / 2 of converged
+ * droplets of several sizes.  out[3] = {sigma_0, delta (Tolman length),
+ * 2 kbar + k (curvature and Gaussian rigidities)}, in lattice units.  SCMC_EINVAL for
+ * NULL pointers, n < 3, non-finite input or fewer than three distinct
+ * curvatures.  Host arrays are borrowed for the call. */
+int scmc_curvature_fit(int n, const double *curvature, const double *sigma, double *out);
 
 /* Flat-interface steady state (Sec. 4: the droplet runs start from the bulk
  * concentrations of a converged flat interface).  Runs the problem's lattice,

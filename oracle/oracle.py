@@ -293,3 +293,15 @@ def excess_com(n, shape):
     com = [c[2] + (ex * x).sum() / total, c[1] + (ex * y).sum() / total,
            c[0] + (ex * z).sum() / total if nz > 1 else 0.0]
     return np.array(com), rich
+
+
+def curvature_fit(curvature, sigma):
+    """Curvature expansion of eq. sigma_c (Sec. 4): the quadratic
+    sigma = c0 + c1 c + c2 c^2 in the signed curvature c = +-1/R_s (negative
+    for droplets of the B-rich phase) fitted by least squares; sigma_0 = c0,
+    the Tolman length delta = -c1 / (2 c0) and 2 kbar + k = c2 / c0."""
+    c = np.asarray(curvature, dtype=np.float64)
+    s = np.asarray(sigma, dtype=np.float64)
+    A = np.stack([np.ones_like(c), c, c * c], axis=1)
+    (c0, c1, c2), *_ = np.linalg.lstsq(A, s, rcond=None)
+    return c0, -c1 / (2.0 * c0), c2 / c0

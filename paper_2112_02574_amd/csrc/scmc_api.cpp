@@ -1021,8 +1021,52 @@ int scmc_run_to_convergence(scmc_sim *s, double R0, int64_t dt, int64_t max_step
         rc = scmc_step(s, k);
         done += k;
         if (!rc) rc = scmc_convergence_check(s, R0, tol_dP, tol_du, out);
+        if (!rc && !std::isfinite(out->dP))
+            rc = fail(s->c, SCMC_ENONFINITE, "Delta P is not finite at step %lld",
+                      (long long)out->step);
     }
     return rc;
+}
+
+int scmc_curvature_fit(int n, const double *curvature, const double *sigma, double *out) {
+    if (n < 3 || !curvature || !sigma || !out) return SCMC_EINVAL;
+    // least squares of sigma = c0 + c1 k + c2 k^2 through the normal equations,
+    // in powers of k / kmax so that the 3 x 3 system stays well scaled
+    double kmax = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(curvature[i]) || !std::isfinite(sigma[i])) return SCMC_EINVAL;
+        kmax = std::max(kmax, std::fabs(curvature[i]));
+    }
+    if (kmax == 0) return SCMC_EINVAL;
+    double A[3][4] = {};
+    for (int i = 0; i < n; ++i) {
+        const double t = curvature[i] / kmax, b[3] = {1.0, t, t * t};
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) A[r][c] += b[r] * b[c];
+            A[r][3] += b[r] * sigma[i];
+        }
+    }
+    const double scale = A[0][0];
+    for (int c = 0; c < 3; ++c) {  // Gauss-Jordan with partial pivoting
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+        if (std::fabs(A[piv][c]) <= 1e-12 * scale) return SCMC_EINVAL;  // < 3 distinct k
+        for (int k = 0; k < 4; ++k) std::swap(A[c][k], A[piv][k]);
+        for (int r = 0; r < 3; ++r) {
+            if (r == c) continue;
+            const double f = A[r][c] / A[c][c];
+            for (int k = c; k < 4; ++k) A[r][k] -= f * A[c][k];
+        }
+    }
+    const double c0 = A[0][3] / A[0][0];
+    const double c1 = A[1][3] / A[1][1] / kmax;
+    const double c2 = A[2][3] / A[2][2] / (kmax * kmax);
+    if (!(c0 != 0) || !std::isfinite(c0)) return SCMC_EINVAL;
+    out[0] = c0;
+    out[1] = -c1 / (2.0 * c0);
+    out[2] = c2 / c0;
+    return SCMC_OK;
 }
 
 int scmc_config(scmc_sim *s, int *kernel, int *tile) {

@@ -128,6 +128,7 @@ _SYMBOLS = {
     "scmc_flat_equilibrium": ([ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
                                ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "scmc_curvature_fit": ([ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "scmc_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
     "scmc_batch_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
     "scmc_status_str": ([ctypes.c_int], ctypes.c_char_p),
@@ -237,6 +238,18 @@ def scmc_flat_equilibrium(p, lx=128, guess=None, max_steps=200000, tol=1e-12,
     if rc:
         raise ScmcError(rc, "scmc_flat_equilibrium")
     return out, steps.value
+
+
+def scmc_curvature_fit(curvature, sigma):
+    """(sigma_0, delta, 2 kbar + k) of eq. sigma_c fitted to signed
+    curvatures 1/R_s (negative for B-rich droplets) and surface tensions."""
+    k = _f64(curvature, len(curvature))
+    sg = _f64(sigma, len(k))
+    out = np.zeros(3)
+    rc = lib().scmc_curvature_fit(len(k), _ptr(k), _ptr(sg), _ptr(out))
+    if rc:
+        raise ScmcError(rc, "scmc_curvature_fit")
+    return tuple(float(v) for v in out)
 
 
 class Sim:
