@@ -52,7 +52,10 @@ template <class R, int PSI> __device__ __forceinline__ R psi_of(R n) {
 }
 
 // Pull the 2Q populations of site (x, y, z) from the post-collision buffer.
-template <int D, class ST>
+// NT: populations with xi_x = 0 (whole cache lines per wavefront) are loaded
+// non-temporally; the shifted ones keep their lines in L2 for the wavefront
+// that shares them.
+template <int D, class ST, bool NT = false>
 __device__ __forceinline__ void pull_site(
     const Member &m, const typename ST::T *__restrict__ src, int x, int y,
     int z, typename ST::R (&f)[2][Lattice<D>::Q]) {
@@ -67,8 +70,14 @@ __device__ __forceinline__ void pull_site(
         const int zs = D == 3 ? wrap1(z - L::CZ[i], m.nz) : 0;
         const long s = ((long)zs * m.ny + ys) * m.nx + xs;
         const R w = (R)L::W[i];
-        f[0][i] = ST::load(base, (long)i * m.N + s, w * n0A);
-        f[1][i] = ST::load(base, (long)(L::Q + i) * m.N + s, w * n0B);
+        if (NT && L::CX[i] == 0) {
+            f[0][i] = ST::from_raw(__builtin_nontemporal_load(base + (long)i * m.N + s), w * n0A);
+            f[1][i] = ST::from_raw(__builtin_nontemporal_load(base + (long)(L::Q + i) * m.N + s),
+                                   w * n0B);
+        } else {
+            f[0][i] = ST::load(base, (long)i * m.N + s, w * n0A);
+            f[1][i] = ST::load(base, (long)(L::Q + i) * m.N + s, w * n0B);
+        }
     }
 }
 
@@ -359,6 +368,9 @@ template <> struct RawBuf<float> {
                                                  int s) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
     }
+    __device__ __forceinline__ static float load_nt(__amdgpu_buffer_rsrc_t r, int v, int s) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, BUF_NT));
+    }
     __device__ __forceinline__ static void store_nt(float x, __amdgpu_buffer_rsrc_t r,
                                                     int v, int s) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v,
@@ -369,6 +381,9 @@ template <> struct RawBuf<uint16_t> {
     __device__ __forceinline__ static uint16_t load(__amdgpu_buffer_rsrc_t r, int v,
                                                     int s) {
         return __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0);
+    }
+    __device__ __forceinline__ static uint16_t load_nt(__amdgpu_buffer_rsrc_t r, int v, int s) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, v, s, BUF_NT);
     }
     __device__ __forceinline__ static void store_nt(uint16_t x,
                                                     __amdgpu_buffer_rsrc_t r, int v,
@@ -397,8 +412,9 @@ __device__ __forceinline__ PopBuf<ST> make_popbuf(const typename ST::T *pop,
     return b;
 }
 
-// Pull of site (x, y, z) through buffer descriptors (D3Q19).
-template <class ST>
+// Pull of site (x, y, z) through buffer descriptors (D3Q19); NT as in
+// pull_site.
+template <class ST, bool NT = false>
 __device__ __forceinline__ void pull_site_buf(const Member &m, const PopBuf<ST> &b,
                                               int x, int y, int z,
                                               typename ST::R (&f)[2][19]) {
@@ -419,8 +435,13 @@ __device__ __forceinline__ void pull_site_buf(const Member &m, const PopBuf<ST> 
         const int s = zo[1 - L::CZ[i]] + yo[1 - L::CY[i]] + xo[1 - L::CX[i]];
         const int voff = s * (int)sizeof(T), soff = i * b.plane_bytes;
         const R w = (R)L::W[i];
-        f[0][i] = ST::from_raw(RawBuf<T>::load(b.r[0], voff, soff), w * n0A);
-        f[1][i] = ST::from_raw(RawBuf<T>::load(b.r[1], voff, soff), w * n0B);
+        if (NT && L::CX[i] == 0) {
+            f[0][i] = ST::from_raw(RawBuf<T>::load_nt(b.r[0], voff, soff), w * n0A);
+            f[1][i] = ST::from_raw(RawBuf<T>::load_nt(b.r[1], voff, soff), w * n0B);
+        } else {
+            f[0][i] = ST::from_raw(RawBuf<T>::load(b.r[0], voff, soff), w * n0A);
+            f[1][i] = ST::from_raw(RawBuf<T>::load(b.r[1], voff, soff), w * n0B);
+        }
     }
 }
 

@@ -130,7 +130,7 @@ __device__ __forceinline__ void moments_site(const Member &m,
                                              int y, int z) {
     using R = typename ST::R;
     R f[2][Lattice<D>::Q], mm[NMOM];
-    pull_site<D, ST>(m, src, x, y, z, f);
+    pull_site<D, ST, true>(m, src, x, y, z, f);
     site_moments<D, R>(f, mm);
     const long s = ((long)z * m.ny + y) * m.nx + x;
     R *base = mom + m.dens_off;
@@ -186,7 +186,7 @@ __device__ __forceinline__ void moments_site_buf(const Member &m, const PopBuf<S
                                                  int y, int z) {
     using R = typename ST::R;
     R f[2][19], mm[NMOM];
-    pull_site_buf<ST>(m, sb, x, y, z, f);
+    pull_site_buf<ST, true>(m, sb, x, y, z, f);
     site_moments<3, R>(f, mm);
     const int s = (z * m.ny + y) * m.nx + x;
     R *base = mom + m.dens_off;
