@@ -52,8 +52,9 @@ typedef enum {
     SCMC_OK = 0,
     SCMC_EINVAL = -1,       /* NULL pointer, bad enum or size, tau <= 1/2,
                                g_AB != g_BA, non-finite input */
-    SCMC_EUNSUPPORTED = -2, /* valid but not implemented (E8 in 3D,
-                               tau_A != tau_B, kernel design for this lattice) */
+    SCMC_EUNSUPPORTED = -2, /* valid but not implemented (E8 in 3D, a tau = 1
+                               design with tau != 1, kernel design for this
+                               lattice) */
     SCMC_ENOSPACE = -3,     /* workspace smaller than scmc_workspace_bytes */
     SCMC_EDEVICE = -4,      /* HIP runtime error; see scmc_last_error */
     SCMC_ENONFINITE = -5,   /* the state holds NaN or Inf */
@@ -113,7 +114,14 @@ typedef struct {
     int stencil;      /* scmc_stencil: isotropy order of the force stencil */
     int nx, ny, nz;   /* periodic box; nz = 1 for D2Q9; every extent
                          >= 2 r_F + 1 where r_F = 1 (E4) or 2 (E6, E8) */
-    double tau[2];    /* BGK relaxation times; must be equal (> 1/2) */
+    double tau[2];    /* BGK relaxation times tau_A, tau_B (> 1/2).  When
+                         they differ, the common velocity weights each
+                         component by 1/tau_J, u = sum_J (j_J + F_J/2)/tau_J
+                         / sum_J n_J/tau_J, which keeps the collision's total
+                         momentum change equal to sum_J F_J and reduces to
+                         the form of Sec. 2 for equal times; the designs
+                         TWO_PASS, FUSED, FUSED_REPULL and FUSED_PIPE run
+                         it */
     double g[2][2];   /* couplings G_JK c_s^2 multiplying the e2 = 1 stencil
                          sums; g[0][1] == g[1][0] is the cross coupling */
     int psi_self;     /* scmc_psi of the self terms; cross terms use n */

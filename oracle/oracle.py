@@ -33,7 +33,7 @@ def build(force=True):
 class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("stencil", ctypes.c_int),
                 ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
-                ("tau", ctypes.c_double), ("g", (ctypes.c_double * 2) * 2),
+                ("tau", ctypes.c_double * 2), ("g", (ctypes.c_double * 2) * 2),
                 ("psi_self", ctypes.c_int), ("nthreads", ctypes.c_int)]
 
 
@@ -132,7 +132,8 @@ class Oracle:
         self.N = nx * ny * nz
         p = _Problem()
         p.dim, p.stencil, p.nx, p.ny, p.nz = dim, stencil, nx, ny, nz
-        p.tau = float(tau)
+        taus = (tau, tau) if np.isscalar(tau) else tuple(tau)
+        p.tau[0], p.tau[1] = float(taus[0]), float(taus[1])
         for J in range(2):
             for K in range(2):
                 p.g[J][K] = float(g[J][K])

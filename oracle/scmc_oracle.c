@@ -137,7 +137,7 @@ int orc_check(const orc_problem *p)
     if (p->dim == 2 && p->nz != 1) return -1;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
     if (orc_stencil(p->dim, p->stencil, e, W) < 0) return -1;
-    if (!(p->tau > 0.5)) return -1;
+    if (!(p->tau[0] > 0.5) || !(p->tau[1] > 0.5)) return -1;
     if (p->psi_self != 0 && p->psi_self != 1) return -1;
     return 0;
 }
@@ -371,21 +371,33 @@ void orc_force(const orc_problem *p, const double *n, double *F)
 }
 
 /* Common velocity (Guo velocity of Sec. 2):
- * (n_A + n_B) u = sum_J [sum_i f_i^J xi_i + F_J / 2]. */
+ * (n_A + n_B) u = sum_J [sum_i f_i^J xi_i + F_J / 2].
+ * With tau_A != tau_B (which the paper does not use) each component is
+ * weighted by 1 / tau_J:
+ * sum_J n_J / tau_J u = sum_J [sum_i f_i^J xi_i + F_J / 2] / tau_J,
+ * the velocity for which the BGK relaxations of the two components change
+ * the total momentum by exactly sum_J F_J. */
 static void velocity_site(const orc_problem *p, const ctx_t *c,
                           const double *f, const double *n, const double *FA,
                           const double *FB, long s, double *u)
 {
     int i, J, k;
     long N = nsites(p);
-    double mom[3] = {0, 0, 0};
+    double mom[2][3] = {{0, 0, 0}, {0, 0, 0}};
     for (J = 0; J < 2; J++)
         for (i = 0; i < c->q; i++)
             for (k = 0; k < 3; k++)
-                mom[k] += f[(J * c->q + i) * N + s] * c->xi[3 * i + k];
+                mom[J][k] += f[(J * c->q + i) * N + s] * c->xi[3 * i + k];
     for (k = 0; k < 3; k++) {
-        mom[k] += 0.5 * FA[k] + 0.5 * FB[k];
-        u[k] = mom[k] / (n[s] + n[N + s]);
+        if (p->tau[0] == p->tau[1]) {
+            u[k] = (mom[0][k] + mom[1][k] + 0.5 * FA[k] + 0.5 * FB[k]) /
+                   (n[s] + n[N + s]);
+        } else {
+            double num = (mom[0][k] + 0.5 * FA[k]) / p->tau[0] +
+                         (mom[1][k] + 0.5 * FB[k]) / p->tau[1];
+            double den = n[s] / p->tau[0] + n[N + s] / p->tau[1];
+            u[k] = num / den;
+        }
     }
 }
 
@@ -412,7 +424,7 @@ void orc_velocity(const orc_problem *p, const double *f, const double *n,
 
 /* BGK collision with Guo forcing for both components at one site
  * (eq. lbm with eq. sm:omega_i):
- * f*_i = f_i - (f_i - f_i^eq(n_J, u)) / tau + (1 - 1/(2 tau)) S_i(u, F_J). */
+ * f*_i = f_i - (f_i - f_i^eq(n_J, u)) / tau_J + (1 - 1/(2 tau_J)) S_i(u, F_J). */
 static void collide_site(const orc_problem *p, const ctx_t *c,
                          const double *f, const double *n, const double *FA,
                          const double *FB, long s, double *out)
@@ -426,8 +438,8 @@ static void collide_site(const orc_problem *p, const ctx_t *c,
         guo_q(q, c->xi, c->w, u, J == 0 ? FA : FB, S);
         for (i = 0; i < q; i++) {
             double fi = f[(J * q + i) * N + s];
-            out[J * q + i] = fi - (fi - feq[i]) / p->tau +
-                             (1.0 - 1.0 / (2.0 * p->tau)) * S[i];
+            out[J * q + i] = fi - (fi - feq[i]) / p->tau[J] +
+                             (1.0 - 1.0 / (2.0 * p->tau[J])) * S[i];
         }
     }
 }
@@ -465,12 +477,13 @@ static void step_rows(const orc_problem *p, const ctx_t *c, const double *f,
     long N = nsites(p);
     int nx = p->nx, q = c->q;
     long nrows = (long)p->ny * p->nz;
-    double omega = 1.0 / p->tau;
+    double omegas[2] = {1.0 / p->tau[0], 1.0 / p->tau[1]};
 #pragma omp parallel
     {
         double *buf = (double *)malloc(sizeof(double) * 26 * nx);
         /* buf rows: sums[J][kind][k] (12 rows: kind 0 = cross, 1 = self),
-         * F[J][k] (6), u[k] (3), tot (1), spare (1), out (1) */
+         * F[J][k] (6), u[k] (3), tot (1), out (1), one component's
+         * momentum (3, unequal tau only) */
         double *sums = buf, *F = buf + 12 * nx, *u = buf + 18 * nx;
         double *tot = buf + 21 * nx;
         long r;
@@ -515,21 +528,44 @@ static void step_rows(const orc_problem *p, const ctx_t *c, const double *f,
                                 sums[((J * 2 + 0) * 3 + k) * nx + x] -
                             p->g[J][J] * psi[J * N + row + x] *
                                 sums[((J * 2 + 1) * 3 + k) * nx + x];
-            /* common velocity */
-            for (J = 0; J < 2; J++)
-                for (i = 0; i < q; i++)
-                    for (k = 0; k < 3; k++) {
-                        double xk = c->xi[3 * i + k];
-                        const double *fr = f + (J * q + i) * N + row;
-                        if (xk == 0.0) continue;
-                        for (x = 0; x < nx; x++) u[k * nx + x] += fr[x] * xk;
-                    }
-            for (x = 0; x < nx; x++)
-                tot[x] = n[row + x] + n[N + row + x];
-            for (k = 0; k < 3; k++)
+            /* common velocity (velocity_site) */
+            if (p->tau[0] == p->tau[1]) {
+                for (J = 0; J < 2; J++)
+                    for (i = 0; i < q; i++)
+                        for (k = 0; k < 3; k++) {
+                            double xk = c->xi[3 * i + k];
+                            const double *fr = f + (J * q + i) * N + row;
+                            if (xk == 0.0) continue;
+                            for (x = 0; x < nx; x++) u[k * nx + x] += fr[x] * xk;
+                        }
                 for (x = 0; x < nx; x++)
-                    u[k * nx + x] = (u[k * nx + x] + 0.5 * F[k * nx + x] +
-                                     0.5 * F[(3 + k) * nx + x]) / tot[x];
+                    tot[x] = n[row + x] + n[N + row + x];
+                for (k = 0; k < 3; k++)
+                    for (x = 0; x < nx; x++)
+                        u[k * nx + x] = (u[k * nx + x] + 0.5 * F[k * nx + x] +
+                                         0.5 * F[(3 + k) * nx + x]) / tot[x];
+            } else {
+                /* each component's momentum + F_J / 2 and density over tau_J */
+                for (x = 0; x < nx; x++)
+                    tot[x] = n[row + x] / p->tau[0] + n[N + row + x] / p->tau[1];
+                for (J = 0; J < 2; J++) {
+                    double *mJ = buf + 23 * nx; /* 3 rows: 23..25 */
+                    for (x = 0; x < 3 * nx; x++) mJ[x] = 0.0;
+                    for (i = 0; i < q; i++)
+                        for (k = 0; k < 3; k++) {
+                            double xk = c->xi[3 * i + k];
+                            const double *fr = f + (J * q + i) * N + row;
+                            if (xk == 0.0) continue;
+                            for (x = 0; x < nx; x++) mJ[k * nx + x] += fr[x] * xk;
+                        }
+                    for (k = 0; k < 3; k++)
+                        for (x = 0; x < nx; x++)
+                            u[k * nx + x] += (mJ[k * nx + x] + 0.5 * F[(J * 3 + k) * nx + x]) /
+                                             p->tau[J];
+                }
+                for (k = 0; k < 3; k++)
+                    for (x = 0; x < nx; x++) u[k * nx + x] /= tot[x];
+            }
             /* collision and streaming */
             for (J = 0; J < 2; J++)
                 for (i = 0; i < q; i++) {
@@ -538,6 +574,7 @@ static void step_rows(const orc_problem *p, const ctx_t *c, const double *f,
                     const double *nJ = n + J * N + row;
                     const double *FJ = F + J * 3 * nx;
                     const double wi = c->w[i];
+                    const double omega = omegas[J];
                     const double x0 = xi[0], x1 = xi[1], x2 = xi[2];
                     long drow =
                         ((long)c->wz[((int)x2 + 2) * p->nz + z] * p->ny +
@@ -810,7 +847,15 @@ void orc_stats(const orc_problem *p, const double *f, double *out)
         if (n[s] < minA) minA = n[s];
         if (n[N + s] < minB) minB = n[N + s];
         for (c = 0; c < 3; c++) {
-            mom[c] += (n[s] + n[N + s]) * u[c * N + s];
+            /* sum_J (sum_i f_i^J xi_i + F_J / 2), which the step conserves
+             * (with equal tau it is (n_A + n_B) u) */
+            double m = 0.5 * (F[c * N + s] + F[(3 + c) * N + s]);
+            int J, i;
+            for (J = 0; J < 2; J++)
+                for (i = 0; i < q; i++)
+                    m += f[(J * q + i) * N + s] *
+                         (p->dim == 2 ? D2Q9_XI[i][c] : D3Q19_XI[i][c]);
+            mom[c] += m;
             un += u[c * N + s] * u[c * N + s];
         }
         if (sqrt(un) > umax) umax = sqrt(un);

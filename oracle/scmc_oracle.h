@@ -31,7 +31,7 @@ typedef struct {
     int dim;          /* 2 -> D2Q9, 3 -> D3Q19 */
     int stencil;      /* isotropy order of the force stencil: 4, 6 or 8 */
     int nx, ny, nz;   /* periodic box; nz must be 1 when dim == 2 */
-    double tau;       /* BGK relaxation time, both components */
+    double tau[2];    /* BGK relaxation times tau_A, tau_B */
     double g[2][2];   /* G_JK c_s^2 */
     int psi_self;     /* self-interaction pseudopotential: 0 -> psi = n,
                          1 -> psi = exp(-1/n); the cross term always uses n */

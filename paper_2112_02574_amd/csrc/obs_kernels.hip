@@ -9,6 +9,19 @@
 
 namespace scmc {
 
+// Common velocity in FP64 from the components' momenta jm[J] = sum_i f_i xi_i:
+// u = sum_J (jm_J + F_J / 2) / (n_A + n_B) (Sec. 2); with tau_A != tau_B both
+// sums are weighted by omega_J = 1 / tau_J, as in the collision.
+__device__ __forceinline__ void common_velocity(const Member &m, const double (&jm)[2][3],
+                                                double nA, double nB, const double (&FA)[3],
+                                                const double (&FB)[3], double (&u)[3]) {
+    const double oA = m.omega[0], oB = m.omega[1];
+    for (int c = 0; c < 3; ++c)
+        u[c] = oA == oB ? (jm[0][c] + jm[1][c] + 0.5 * (FA[c] + FB[c])) / (nA + nB)
+                        : (oA * (jm[0][c] + 0.5 * FA[c]) + oB * (jm[1][c] + 0.5 * FB[c])) /
+                              (oA * nA + oB * nB);
+}
+
 constexpr int OB_BX = 64, OB_BY = 4, OB_THREADS = OB_BX * OB_BY;
 
 // Population value as a double: the stored value plus, for the offset
@@ -102,21 +115,21 @@ __global__ void __launch_bounds__(OB_THREADS)
         double FA[3], FB[3];
         site_force<D, ORDER, PSI, double>(m, dens, dens + m.N, x, y, z, nA,
                                           nB, FA, FB);
-        double mom[3] = {0, 0, 0}, bad = 0;
+        double jm[2][3] = {{0, 0, 0}, {0, 0, 0}}, bad = 0;
 #pragma unroll
         for (int J = 0; J < 2; ++J)
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) {
                 if (!isfinite(f[J][i])) bad += 1;
-                mom[0] += L::CX[i] * f[J][i];
-                mom[1] += L::CY[i] * f[J][i];
-                mom[2] += L::CZ[i] * f[J][i];
+                jm[J][0] += L::CX[i] * f[J][i];
+                jm[J][1] += L::CY[i] * f[J][i];
+                jm[J][2] += L::CZ[i] * f[J][i];
             }
-        double uu = 0;
+        double mom[3], u[3], uu = 0;
+        common_velocity(m, jm, nA, nB, FA, FB, u);
         for (int c = 0; c < 3; ++c) {
-            mom[c] += 0.5 * (FA[c] + FB[c]);
-            const double u = mom[c] / (nA + nB);
-            uu += u * u;
+            mom[c] = jm[0][c] + jm[1][c] + 0.5 * (FA[c] + FB[c]);
+            uu += u[c] * u[c];
         }
         v[0] = nA;
         v[1] = nB;
@@ -180,17 +193,17 @@ __global__ void __launch_bounds__(OB_THREADS)
     double FA[3], FB[3];
     site_force<D, ORDER, PSI, double>(m, dens, dens + m.N, x, y, z, nA, nB,
                                       FA, FB);
-    double mom[3] = {0, 0, 0};
+    double jm[2][3] = {{0, 0, 0}, {0, 0, 0}}, us[3];
 #pragma unroll
     for (int J = 0; J < 2; ++J)
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            mom[0] += L::CX[i] * f[J][i];
-            mom[1] += L::CY[i] * f[J][i];
-            mom[2] += L::CZ[i] * f[J][i];
+            jm[J][0] += L::CX[i] * f[J][i];
+            jm[J][1] += L::CY[i] * f[J][i];
+            jm[J][2] += L::CZ[i] * f[J][i];
         }
-    for (int c = 0; c < 3; ++c)
-        u[(long)c * m.N + s] = (mom[c] + 0.5 * (FA[c] + FB[c])) / (nA + nB);
+    common_velocity(m, jm, nA, nB, FA, FB, us);
+    for (int c = 0; c < 3; ++c) u[(long)c * m.N + s] = us[c];
 }
 
 // Lattice pressure tensor (eq. sm:pt) at one site, FP64:

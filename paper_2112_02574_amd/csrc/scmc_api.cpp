@@ -209,6 +209,9 @@ int fail(Common &c, int status, const char *fmt, ...) {
                         hipGetErrorString(e_));                              \
     } while (0)
 
+// The tau = 1 designs need both relaxation times equal to one.
+static bool tau_is_one(const scmc_problem &p) { return p.tau[0] == 1.0 && p.tau[1] == 1.0; }
+
 int validate(const scmc_problem *p, std::string *why) {
     char buf[256];
     auto bad = [&](int st, const char *msg) {
@@ -244,12 +247,10 @@ int validate(const scmc_problem *p, std::string *why) {
     for (int J = 0; J < 2; ++J)
         if (!std::isfinite(p->tau[J]) || !(p->tau[J] > 0.5))
             return bad(SCMC_EINVAL, "tau must be finite and > 1/2");
-    if (p->tau[0] != p->tau[1])
-        return bad(SCMC_EUNSUPPORTED, "tau_A != tau_B is not supported");
     if ((p->kernel == SCMC_KERNEL_FUSED_MOM || p->kernel == SCMC_KERNEL_FUSED_MOM_PIPE ||
          p->kernel == SCMC_KERNEL_TWO_PASS_MOM) &&
-        p->tau[0] != 1.0)
-        return bad(SCMC_EUNSUPPORTED, "the moment-ring designs need tau = 1");
+        !tau_is_one(*p))
+        return bad(SCMC_EUNSUPPORTED, "the moment-ring designs need tau_A = tau_B = 1");
     for (int J = 0; J < 2; ++J)
         for (int K = 0; K < 2; ++K)
             if (!std::isfinite(p->g[J][K])) return bad(SCMC_EINVAL, "non-finite coupling");
@@ -279,10 +280,10 @@ StepKey key_of(const scmc_problem &p) {
         case SCMC_KERNEL_FUSED_PIPE: k.repull = 2; break;
         case SCMC_KERNEL_FUSED_MOM: k.repull = 3; break;
         case SCMC_KERNEL_FUSED_MOM_PIPE: k.repull = 4; break;
-        case SCMC_KERNEL_AUTO: k.repull = p.tau[0] == 1.0 ? 3 : 0; break;
+        case SCMC_KERNEL_AUTO: k.repull = tau_is_one(p) ? 3 : 0; break;
         default: k.repull = 0;
     }
-    k.mom = p.tau[0] == 1.0 && (p.kernel == SCMC_KERNEL_TWO_PASS_MOM ||
+    k.mom = tau_is_one(p) && (p.kernel == SCMC_KERNEL_TWO_PASS_MOM ||
                                 p.kernel == SCMC_KERNEL_AUTO);
     // TWO_PASS_MOM with a tile asks for the LDS-staged collision pass (its
     // shape is fixed at 64 x 8 columns and z-chunks of 8)
@@ -304,7 +305,8 @@ Member member_of(const scmc_problem &p) {
     m.dens_off = 0;
     for (int J = 0; J < 2; ++J)
         for (int K = 0; K < 2; ++K) m.g[J][K] = p.g[J][K];
-    m.omega = 1.0 / p.tau[0];
+    m.omega[0] = 1.0 / p.tau[0];
+    m.omega[1] = 1.0 / p.tau[1];
     m.n0[0] = p.n0[0];
     m.n0[1] = p.n0[1];
     m.psi_self = p.psi_self;
@@ -1202,6 +1204,7 @@ static int batch_check(const scmc_problem *ps, int count, std::string *why) {
         if (rc) return rc;
         if (ps[i].lattice != ps[0].lattice || ps[i].stencil != ps[0].stencil ||
             ps[i].storage != ps[0].storage || ps[i].tau[0] != ps[0].tau[0] ||
+            ps[i].tau[1] != ps[0].tau[1] ||
             ps[i].psi_self != ps[0].psi_self || ps[i].kernel != ps[0].kernel ||
             ps[i].rounding != ps[0].rounding ||
             ps[i].tile[0] != ps[0].tile[0] || ps[i].tile[1] != ps[0].tile[1] ||
@@ -1410,7 +1413,7 @@ std::vector<Candidate> candidates(const scmc_problem &p, const StepKey &k0, int 
     static const int tiles[][2] = {{64, 4}, {32, 8},  {64, 8}, {32, 16},
                                    {128, 4}, {128, 8}, {64, 16}};
     static const int chunks[] = {8, 16, 32};
-    const bool tau1 = p.tau[0] == 1.0;
+    const bool tau1 = tau_is_one(p);
     std::vector<int> variants;
     if (p.kernel == SCMC_KERNEL_AUTO) {
         variants = {0, 2};
@@ -1450,7 +1453,7 @@ std::string cache_key(const scmc_problem &p, int count) {
     snprintf(buf, sizeof buf,
              "lattice=%d stencil=%d storage=%d psi=%d rounding=%d tau1=%d kernel=%d "
              "box=%dx%dx%d members=%d",
-             p.lattice, p.stencil, p.storage, p.psi_self, p.rounding, p.tau[0] == 1.0 ? 1 : 0,
+             p.lattice, p.stencil, p.storage, p.psi_self, p.rounding, tau_is_one(p) ? 1 : 0,
              p.kernel, p.nx, p.ny, p.nz, count);
     return buf;
 }

@@ -17,7 +17,7 @@ struct Member {
     long long pop_off;
     long long dens_off;
     double g[2][2];   // G_JK c_s^2
-    double omega;     // 1 / tau
+    double omega[2];  // 1 / tau_J
     double n0[2];     // offset references (FP16 / BF16 storage)
     int psi_self;     // 0: psi = n, 1: psi = exp(-1/n)
     int self_on;      // bit J set when g_JJ != 0

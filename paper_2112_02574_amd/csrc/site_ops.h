@@ -5,7 +5,7 @@
 //   force:    F_J = -g_JK n_J sum_a W_a n_K(x + e_a) e_a
 //                   -g_JJ psi_J sum_a W_a psi_J(x + e_a) e_a   (eq. sc_force)
 //   velocity: (n_A + n_B) u = sum_J [sum_i f_i^J xi_i + F_J / 2]
-//   collide:  f* = f - omega (f - f^eq(n_J, u)) + (1 - omega/2) S_i(u, F_J)
+//   collide:  f* = f - omega_J (f - f^eq(n_J, u)) + (1 - omega_J/2) S_i(u, F_J)
 //             f^eq = n w_i [1 + 3 xi.u + 9/2 (xi.u)^2 - 3/2 u.u]
 //             S_i  = w_i [3 xi.F + 9 (xi.u)(xi.F) - 3 u.F]     (c_s^2 = 1/3)
 #pragma once
@@ -184,21 +184,34 @@ __device__ __forceinline__ void site_collide(const Member &m,
                                              R nA, R nB, const R (&FA)[3],
                                              const R (&FB)[3], Sink &&sink) {
     using L = Lattice<D>;
-    double mx = 0, my = 0, mz = 0;  // order-free sums (see site_density)
+    double jx[2] = {0, 0}, jy[2] = {0, 0}, jz[2] = {0, 0};  // order-free sums (see site_density)
 #pragma unroll
     for (int J = 0; J < 2; ++J)
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            if (L::CX[i]) mx += (double)L::CX[i] * (double)f[J][i];
-            if (L::CY[i]) my += (double)L::CY[i] * (double)f[J][i];
-            if (D == 3 && L::CZ[i]) mz += (double)L::CZ[i] * (double)f[J][i];
+            if (L::CX[i]) jx[J] += (double)L::CX[i] * (double)f[J][i];
+            if (L::CY[i]) jy[J] += (double)L::CY[i] * (double)f[J][i];
+            if (D == 3 && L::CZ[i]) jz[J] += (double)L::CZ[i] * (double)f[J][i];
         }
-    const R inv = R(1) / (nA + nB);
-    const R ux = ((R)mx + R(0.5) * (FA[0] + FB[0])) * inv;
-    const R uy = ((R)my + R(0.5) * (FA[1] + FB[1])) * inv;
-    const R uz = D == 3 ? ((R)mz + R(0.5) * (FA[2] + FB[2])) * inv : R(0);
+    R ux, uy, uz;
+    if (m.omega[0] == m.omega[1]) {
+        // common velocity of Sec. 2
+        const R inv = R(1) / (nA + nB);
+        ux = ((R)(jx[0] + jx[1]) + R(0.5) * (FA[0] + FB[0])) * inv;
+        uy = ((R)(jy[0] + jy[1]) + R(0.5) * (FA[1] + FB[1])) * inv;
+        uz = D == 3 ? ((R)(jz[0] + jz[1]) + R(0.5) * (FA[2] + FB[2])) * inv : R(0);
+    } else {
+        // tau_A != tau_B: each component's momentum and density weighted by
+        // omega_J = 1 / tau_J, the form under which the collisions change the
+        // total momentum by exactly sum_J F_J
+        const R oA = (R)m.omega[0], oB = (R)m.omega[1];
+        const R inv = R(1) / (oA * nA + oB * nB);
+        ux = (oA * ((R)jx[0] + R(0.5) * FA[0]) + oB * ((R)jx[1] + R(0.5) * FB[0])) * inv;
+        uy = (oA * ((R)jy[0] + R(0.5) * FA[1]) + oB * ((R)jy[1] + R(0.5) * FB[1])) * inv;
+        uz = D == 3 ? (oA * ((R)jz[0] + R(0.5) * FA[2]) + oB * ((R)jz[1] + R(0.5) * FB[2])) * inv
+                    : R(0);
+    }
     const R uu = ux * ux + uy * uy + uz * uz;
-    const R omega = (R)m.omega, keep = R(1) - omega, cf = R(1) - R(0.5) * omega;
     const R n0[2] = {(R)m.n0[0], (R)m.n0[1]};
     constexpr Opposite<D> OP = Opposite<D>::make();
     // Velocities xi and -xi are collided together: with t = omega n_J xi.u,
@@ -210,6 +223,7 @@ __device__ __forceinline__ void site_collide(const Member &m,
     // covariant under mirror reflections (see site_density).
 #pragma unroll
     for (int J = 0; J < 2; ++J) {
+        const R omega = (R)m.omega[J], keep = R(1) - omega, cf = R(1) - R(0.5) * omega;
         const R *F = J == 0 ? FA : FB;
         const R nJ = J == 0 ? nA : nB;
         const R uF = ux * F[0] + uy * F[1] + uz * F[2];

@@ -62,7 +62,7 @@ class Naive:
         self.sten = stencil(dim, order)
         nz, ny, nx = shape if dim == 3 else (1,) + tuple(shape)
         self.size = (nx, ny, nz)
-        self.tau = tau
+        self.taus = (tau, tau) if np.isscalar(tau) else tuple(tau)
         self.g = g
         self.psi_self = psi_self
         self.nodes = [(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)]
@@ -94,22 +94,49 @@ class Naive:
                     acc -= (self.g[J][J] * _psi(n[J][p], self.psi_self) * W *
                             _psi(n[J][q], self.psi_self) * np.array(e, float))
                 F.append(acc)
-            mom = np.zeros(3)
+            def collide(u):
+                res = []
+                for J in range(2):
+                    tau = self.taus[J]
+                    out = {}
+                    for v, w in self.vel:
+                        xi = np.array(v, float)
+                        H2 = np.outer(xi, xi) - CS2 * np.eye(3)
+                        feq = n[J][p] * w * (1.0 + xi @ u / CS2 + np.sum(H2 * np.outer(u, u)) / (2 * CS2 ** 2))
+                        S = w * (xi @ F[J] / CS2 + np.sum(H2 * np.outer(u, F[J])) / CS2 ** 2)
+                        fv = self.f[J][p][v]
+                        out[v] = fv + (-(fv - feq) / tau) + (1.0 - 1.0 / (2 * tau)) * S
+                    res.append(out)
+                return res
+
+            if self.taus[0] == self.taus[1]:
+                mom = np.zeros(3)
+                for J in range(2):
+                    for v, fv in self.f[J][p].items():
+                        mom += fv * np.array(v, float)
+                    mom += 0.5 * F[J]
+                u = mom / (n[0][p] + n[1][p])
+            else:
+                # the velocity for which the collision changes the total
+                # momentum by exactly F_A + F_B: the change is affine in u, so
+                # probe it at u = 0 and the unit vectors and solve
+                def excess(u):
+                    out = collide(u)
+                    d = -(F[0] + F[1])
+                    for J in range(2):
+                        for v, fv in out[J].items():
+                            d = d + (fv - self.f[J][p][v]) * np.array(v, float)
+                    return d
+                d0 = excess(np.zeros(3))
+                A = np.stack([excess(np.eye(3)[k]) - d0 for k in range(3)], axis=1)
+                if self.dim == 2:
+                    u = np.zeros(3)
+                    u[:2] = np.linalg.solve(A[:2, :2], -d0[:2])
+                else:
+                    u = np.linalg.solve(A, -d0)
+            post_p = collide(u)
             for J in range(2):
-                for v, fv in self.f[J][p].items():
-                    mom += fv * np.array(v, float)
-                mom += 0.5 * F[J]
-            u = mom / (n[0][p] + n[1][p])
-            for J in range(2):
-                out = {}
-                for v, w in self.vel:
-                    xi = np.array(v, float)
-                    H2 = np.outer(xi, xi) - CS2 * np.eye(3)
-                    feq = n[J][p] * w * (1.0 + xi @ u / CS2 + np.sum(H2 * np.outer(u, u)) / (2 * CS2 ** 2))
-                    S = w * (xi @ F[J] / CS2 + np.sum(H2 * np.outer(u, F[J])) / CS2 ** 2)
-                    fv = self.f[J][p][v]
-                    out[v] = fv + (-(fv - feq) / self.tau) + (1.0 - 1.0 / (2 * self.tau)) * S
-                post[J][p] = out
+                post[J][p] = post_p[J]
         new = [dict(), dict()]
         for J in range(2):
             for p in self.nodes:

@@ -64,7 +64,9 @@ def test_workspace_planner():
     (lambda p: setattr(p, "stencil", scmc.E8), -2),        # E8 is 2D only
     (lambda p: setattr(p, "nx", 4), -1),                   # < 2 r_F + 1 for E6
     (lambda p: p.tau.__setitem__(0, 0.5), -1),
-    (lambda p: p.tau.__setitem__(1, 0.9), -2),             # tau_A != tau_B
+    (lambda p: p.tau.__setitem__(1, 0.4), -1),
+    (lambda p: (setattr(p, "kernel", scmc.KERNEL_TWO_PASS_MOM),
+                p.tau.__setitem__(1, 0.9)), -2),          # tau = 1 design, tau_B != 1
     (lambda p: p.g[0].__setitem__(1, 1.7), -1),            # g_AB != g_BA
     (lambda p: p.g[0].__setitem__(0, float("nan")), -1),
     (lambda p: setattr(p, "storage", 9), -1),
@@ -118,3 +120,12 @@ def test_batch_members_must_share_lattice():
     arr = (scmc.Problem * 2)(a, c)
     assert scmc.lib().scmc_batch_workspace_bytes(arr, 2, ctypes.byref(out)) == 0
     assert out.value > 2 * 2 * 19 * 4 * (48 ** 3 + 56 * 64 * 72)
+
+
+def test_unequal_tau_is_accepted_by_the_tau_general_designs():
+    for kernel in (scmc.KERNEL_AUTO, scmc.KERNEL_TWO_PASS, scmc.KERNEL_FUSED):
+        p = scmc.problem(scmc.D3Q19, scmc.E6, (16, 16, 16), kernel=kernel)
+        p.tau[0], p.tau[1] = 0.7, 1.45
+        out = ctypes.c_size_t()
+        assert scmc.lib().scmc_workspace_bytes(ctypes.byref(p), ctypes.byref(out)) == 0
+        assert out.value > 0

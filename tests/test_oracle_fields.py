@@ -186,3 +186,66 @@ def test_excess_com_locates_the_droplet():
     assert np.abs(com2 - (L // 2 + np.array([2, -1, 1]))).max() < 1e-7
     com3, rich3 = O.excess_com(np.stack([nB, nA]), (L, L, L))
     assert rich3 == 1 and np.abs(com3 - L // 2).max() < 1e-8
+
+
+@pytest.mark.parametrize("dim,order,shape,psi", [
+    (2, 4, (8, 8), O.PSI_N), (2, 8, (8, 7), O.PSI_EXP), (3, 6, (5, 6, 6), O.PSI_N)])
+def test_brute_force_agreement_unequal_tau(dim, order, shape, psi):
+    """tau_A != tau_B: the brute-force stepper finds the common velocity as the
+    one for which the collision changes the total momentum by exactly
+    F_A + F_B (solving that linear condition, not using a formula)."""
+    rng = np.random.default_rng(24)
+    g = ((-0.2, 1.8), (1.8, 0.0)) if psi == O.PSI_N else ((-0.9, 1.2), (1.2, -0.5))
+    tau = (0.7, 1.45)
+    nA = rng.uniform(0.2, 1.0, shape)
+    nB = rng.uniform(0.2, 1.0, shape)
+    o = O.Oracle(dim, order, shape, tau=tau, g=g, psi_self=psi)
+    o.set_density(nA, nB)
+    nv = Naive(dim, order, shape, tau, g, psi)
+    nv.set_density(nA, nB)
+    steps = 5 if dim == 3 else 10
+    o.run(steps)
+    for _ in range(steps):
+        nv.step()
+    fn = nv.populations()[:, _vel_map(dim, nv)]
+    assert np.abs(o.f - fn.reshape(o.f.shape)).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim,order", [(2, 8), (3, 6)])
+def test_unequal_tau_conserves_momentum(dim, order):
+    """With tau_A != tau_B the weighted common velocity keeps the total
+    momentum (the forces sum to zero on the periodic lattice) and each
+    component's mass; the unweighted velocity of Sec. 2 would not."""
+    rng = np.random.default_rng(25)
+    L = 24 if dim == 2 else 12
+    shape = (L, L) if dim == 2 else (L, L, L)
+    o = O.Oracle(dim, order, shape, tau=(0.65, 1.6), g=((-0.05, 1.4), (1.4, 0.05)))
+    nA, nB = inputs.droplet(L, L, None if dim == 2 else L, R=L / 4)
+    o.set_density(nA + 2e-3 * rng.uniform(-1, 1, shape), nB)
+    s0 = o.stats()
+    o.run(300 if dim == 2 else 60)
+    s1 = o.stats()
+    np.testing.assert_allclose(s1["mass"], s0["mass"], rtol=1e-13)
+    assert np.abs(s1["momentum"]).max() < 1e-11 * s0["mass"].sum()
+    assert s1["max_u"] > 1e-5
+
+
+def test_shear_wave_of_one_component_with_unequal_tau():
+    """Only component A present (n_B = 0): the weighted velocity is A's own,
+    and a shear wave decays with A's viscosity c_s^2 (tau_A - 1/2) whatever
+    tau_B is."""
+    L, tauA = 64, 0.8
+    o = O.Oracle(2, 4, (L, 4), tau=(tauA, 1.7), g=((0.0, 0.0), (0.0, 0.0)))
+    k, U = 2 * np.pi / L, 1e-4
+    f = np.zeros((2, 9, 1, L, 4))
+    for iy in range(L):
+        f[0, :, 0, iy, :] = O.equilibrium(2, 0.7, np.array([U * np.sin(k * iy), 0.0, 0.0]))[:, None]
+    o.set_populations(f)
+
+    def amp():
+        u = o.velocity()[0, 0, :, 0]
+        return 2.0 / L * np.sum(u * np.sin(k * np.arange(L)))
+    a0 = amp()
+    o.run(400)
+    nu = -np.log(amp() / a0) / (k * k * 400)
+    assert abs(nu / ((tauA - 0.5) / 3.0) - 1.0) < 2e-3
