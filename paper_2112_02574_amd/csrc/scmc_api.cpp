@@ -187,6 +187,11 @@ struct scmc_batch {
     int ntiles_cap = 0;  // tile-list capacity planned in the workspace
     int grid = 0;
     std::vector<bool> member_set;
+    // The moment two-pass runs the tile list in chunks of whole members, each
+    // chunk's pass 2 right after its pass 1, so that the chunk's moment field
+    // (24 B per site in FP32) is still in the caches; chunks[k] is the first
+    // tile of chunk k and chunks.back() == ntiles.
+    std::vector<int> chunks;
 };
 
 namespace {
@@ -664,13 +669,17 @@ int direct_step_batch(scmc_batch *b) {
     Common &c = b->c;
     const void *src = c.pop[c.cur];
     void *dst = c.pop[1 - c.cur];
-    hipError_t e =
-        c.kernel == SCMC_KERNEL_FUSED
-            ? launch_batch_fused(c.key, b->d_members, b->d_tiles, b->ntiles,
-                                 src, dst, c.tile, b->grid, c.stream)
-            : launch_batch_two_pass(c.key, b->d_members, b->d_tiles,
-                                    b->ntiles, src, dst, c.dens, b->grid,
-                                    c.stream);
+    hipError_t e = hipSuccess;
+    if (c.kernel == SCMC_KERNEL_FUSED) {
+        e = launch_batch_fused(c.key, b->d_members, b->d_tiles, b->ntiles, src, dst, c.tile,
+                               b->grid, c.stream);
+    } else {
+        for (size_t k = 0; e == hipSuccess && k + 1 < b->chunks.size(); ++k) {
+            const int t0 = b->chunks[k], nt = b->chunks[k + 1] - t0;
+            e = launch_batch_two_pass(c.key, b->d_members, b->d_tiles + t0, nt, src, dst,
+                                      c.dens, std::min(b->grid, nt), c.stream);
+        }
+    }
     if (e != hipSuccess)
         return fail(c, SCMC_EDEVICE, "batch step launch: %s",
                     hipGetErrorString(e));
@@ -691,80 +700,70 @@ struct ArgPack {
     int tile[3];
 };
 
+// A batch runs its tile list as the chunks [chunks[j], chunks[j + 1]) (one
+// chunk {0, 0} for a single lattice, {0, ntiles} for the fused designs).
 int build_graph(Common &c, int k, int par, bool batch, const Member &m,
-                const Member *d_members, const Tile *d_tiles, int ntiles,
-                int grid) {
+                const Member *d_members, const Tile *d_tiles,
+                const std::vector<int> &chunks, int grid) {
     hipGraph_t g = nullptr;
     HIPCHK(c, hipGraphCreate(&g, 0));
     hipGraphNode_t prev = nullptr;
-    NodeLaunch dn{}, sn{};
-    bool fused = c.kernel == SCMC_KERNEL_FUSED;
-    bool ok = batch ? (fused ? node_batch_fused(c.key, c.tile, grid, &sn)
-                             : node_batch_two_pass(c.key, grid, &dn, &sn))
-                    : (fused ? node_fused(c.key, c.tile, &sn, m)
-                             : node_two_pass(c.key, &dn, &sn, m));
-    if (!ok) {
-        (void)hipGraphDestroy(g);
-        return fail(c, SCMC_EUNSUPPORTED, "no graph node for this kernel");
-    }
-    int cur = par;
-    for (int t = 0; t < k; ++t) {
-        const void *src = c.pop[cur];
-        void *dst = c.pop[1 - cur];
-        // argument values, in kernel-signature order
-        Member mv = m;
-        const Member *dm = d_members;
-        const Tile *dt = d_tiles;
-        int nt = ntiles;
-        const void *srcv = src;
-        void *dstv = dst;
-        void *densv = c.dens;
-        int zc = c.tile[2];
-        // the step kernel's last argument: the density field (two-pass) or
-        // the z-chunk length (fused)
-        void *last = fused ? (void *)&zc : (void *)&densv;
-        std::vector<void *> dargs, sargs;
-        if (batch) {
-            dargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
-                     (void *)&densv};
-            sargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
-                     (void *)&dstv, last};
-        } else {
-            dargs = {(void *)&mv, (void *)&srcv, (void *)&densv};
-            sargs = {(void *)&mv, (void *)&srcv, (void *)&dstv, last};
-        }
-        if (!fused) {
-            hipKernelNodeParams kp{};
-            kp.func = dn.func;
-            kp.gridDim = dn.grid;
-            kp.blockDim = dn.block;
-            kp.sharedMemBytes = dn.shmem;
-            kp.kernelParams = dargs.data();
-            hipGraphNode_t node;
-            hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr,
-                                                 prev ? 1 : 0, &kp);
-            if (e != hipSuccess) {
-                (void)hipGraphDestroy(g);
-                return fail(c, SCMC_EDEVICE, "graph node: %s",
-                            hipGetErrorString(e));
-            }
-            prev = node;
-        }
+    const bool fused = c.kernel == SCMC_KERNEL_FUSED;
+    auto add = [&](const NodeLaunch &nl, std::vector<void *> &args) -> int {
         hipKernelNodeParams kp{};
-        kp.func = sn.func;
-        kp.gridDim = sn.grid;
-        kp.blockDim = sn.block;
-        kp.sharedMemBytes = sn.shmem;
-        kp.kernelParams = sargs.data();
+        kp.func = nl.func;
+        kp.gridDim = nl.grid;
+        kp.blockDim = nl.block;
+        kp.sharedMemBytes = nl.shmem;
+        kp.kernelParams = args.data();
         hipGraphNode_t node;
-        hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr,
-                                             prev ? 1 : 0, &kp);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(g);
-            return fail(c, SCMC_EDEVICE, "graph node: %s", hipGetErrorString(e));
-        }
+        hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (e != hipSuccess) return fail(c, SCMC_EDEVICE, "graph node: %s", hipGetErrorString(e));
         prev = node;
+        return SCMC_OK;
+    };
+    int cur = par, rc = SCMC_OK;
+    for (int t = 0; t < k && !rc; ++t) {
+        for (size_t ch = 0; ch + 1 < chunks.size() && !rc; ++ch) {
+            const int ntiles = chunks[ch + 1] - chunks[ch];
+            const int cgrid = batch ? std::min(grid, ntiles) : grid;
+            NodeLaunch dn{}, sn{};
+            const bool ok = batch ? (fused ? node_batch_fused(c.key, c.tile, cgrid, &sn)
+                                           : node_batch_two_pass(c.key, cgrid, &dn, &sn))
+                                  : (fused ? node_fused(c.key, c.tile, &sn, m)
+                                           : node_two_pass(c.key, &dn, &sn, m));
+            if (!ok) {
+                rc = fail(c, SCMC_EUNSUPPORTED, "no graph node for this kernel");
+                break;
+            }
+            // argument values, in kernel-signature order
+            Member mv = m;
+            const Member *dm = d_members;
+            const Tile *dt = d_tiles ? d_tiles + chunks[ch] : nullptr;
+            int nt = ntiles;
+            const void *srcv = c.pop[cur];
+            void *dstv = c.pop[1 - cur];
+            void *densv = c.dens;
+            int zc = c.tile[2];
+            // the step kernel's last argument: the density field (two-pass) or
+            // the z-chunk length (fused)
+            void *last = fused ? (void *)&zc : (void *)&densv;
+            std::vector<void *> dargs, sargs;
+            if (batch) {
+                dargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv, (void *)&densv};
+                sargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv, (void *)&dstv, last};
+            } else {
+                dargs = {(void *)&mv, (void *)&srcv, (void *)&densv};
+                sargs = {(void *)&mv, (void *)&srcv, (void *)&dstv, last};
+            }
+            if (!fused) rc = add(dn, dargs);
+            if (!rc) rc = add(sn, sargs);
+        }
         cur ^= 1;
+    }
+    if (rc) {
+        (void)hipGraphDestroy(g);
+        return rc;
     }
     hipError_t e = hipGraphInstantiate(&c.gexec[par], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -926,8 +925,9 @@ int scmc_step(scmc_sim *s, int64_t nsteps) {
     return run_steps(
         c, nsteps, [&] { return direct_step_sim(s); },
         [&](int par) {
+            static const std::vector<int> whole = {0, 0};
             return build_graph(c, c.graph_k, par, false, s->lat.m, nullptr,
-                               nullptr, 0, 0);
+                               nullptr, whole, 0);
         });
 }
 
@@ -1184,6 +1184,35 @@ static int batch_tiles(const std::vector<scmc_problem> &ps, int kernel,
     return (int)out->size();
 }
 
+// Chunks of whole members for the batched moment two-pass (see scmc_batch):
+// members join a chunk until its moment fields would pass kBatchChunkBytes.
+// The fused designs, the other two-pass forms and stochastic rounding (whose
+// step counter advances at the first tile of a launch) run the whole list.
+static constexpr size_t kBatchChunkBytes = (size_t)48 << 20;
+
+static void batch_set_chunks(scmc_batch *b) {
+    const Common &c = b->c;
+    bool chunked = c.kernel != SCMC_KERNEL_FUSED && c.key.mom;
+    for (const Lat &L : b->lats) chunked = chunked && !L.m.sr;
+    std::vector<int> ch = {0};
+    if (chunked) {
+        int t = 0;
+        size_t bytes = 0;
+        for (const Lat &L : b->lats) {
+            const size_t mb = (size_t)6 * L.m.N * real_bytes(L.p.storage);
+            if (t > ch.back() && bytes + mb > kBatchChunkBytes) {
+                ch.push_back(t);
+                bytes = 0;
+            }
+            t += (L.m.N + 255) / 256;  // the two-pass tiles of batch_tiles
+            bytes += mb;
+        }
+        if (t != b->ntiles) ch = {0};
+    }
+    ch.push_back(b->ntiles);
+    b->chunks = ch;
+}
+
 // Tile-list capacity: enough for the current design, for the smallest fused
 // tile and for the two-pass tiling, so that the autotuner can switch design
 // and tile inside the same workspace.
@@ -1295,6 +1324,7 @@ int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
             ncu = prop.multiProcessorCount;
     }
     b->grid = std::min(b->ntiles, ncu * 8);
+    batch_set_chunks(b);
     hipError_t e = hipMemcpyAsync(b->d_members, ms.data(),
                                   ms.size() * sizeof(Member),
                                   hipMemcpyHostToDevice, c.stream);
@@ -1354,7 +1384,7 @@ int scmc_batch_step(scmc_batch *b, int64_t nsteps) {
         c, nsteps, [&] { return direct_step_batch(b); },
         [&](int par) {
             return build_graph(c, c.graph_k, par, true, Member{}, b->d_members,
-                               b->d_tiles, b->ntiles, b->grid);
+                               b->d_tiles, b->chunks, b->grid);
         });
 }
 
@@ -1604,6 +1634,7 @@ int scmc_batch_autotune(scmc_batch *b, const char *cache_path, int *tile) {
             return fail(c, SCMC_ENOSPACE, "tile list larger than planned");
         apply(c, cand);
         b->ntiles = nt;
+        batch_set_chunks(b);
         HIPCHK(c, hipMemcpyAsync(b->d_tiles, tiles.data(), nt * sizeof(Tile),
                                  hipMemcpyHostToDevice, c.stream));
         HIPCHK(c, hipStreamSynchronize(c.stream));
