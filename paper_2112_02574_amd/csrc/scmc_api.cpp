@@ -756,6 +756,18 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
                 dargs = {(void *)&mv, (void *)&srcv, (void *)&densv};
                 sargs = {(void *)&mv, (void *)&srcv, (void *)&dstv, last};
             }
+            const std::vector<SlabOp> slabs =
+                batch || fused ? std::vector<SlabOp>() : slab_schedule(c.key, m);
+            if (!slabs.empty()) {  // the moment two-pass in z-slabs, as launch_two_pass
+                for (const SlabOp &o : slabs) {
+                    NodeLaunch nl = o.pass == 1 ? dn : sn;
+                    nl.grid.z = o.nz;
+                    mv = m;
+                    mv.zoff = o.z0;
+                    if (!rc) rc = add(nl, o.pass == 1 ? dargs : sargs);
+                }
+                continue;
+            }
             if (!fused) rc = add(dn, dargs);
             if (!rc) rc = add(sn, sargs);
         }

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace scmc {
 
 // One lattice as the kernels see it.  Populations of a member live at
@@ -25,6 +27,7 @@ struct Member {
     unsigned seed;    // its seed
     unsigned *step_ctr;  // device step counter: advanced by the first pass of
                          // a two-pass step, read by the second (random stream)
+    int zoff;            // first z-plane of a slab launch (moment two-pass)
 };
 
 // A unit of work of the batched launches: member index and tile origin.
@@ -72,6 +75,15 @@ struct NodeLaunch {
     dim3 grid, block;
     unsigned shmem;
 };
+// The moment two-pass over a lattice whose moment field does not fit the
+// caches runs in z-slabs: pass 2 of a slab follows pass 1 of the next one, so
+// the moments it gathers are still cached.  Empty: one launch per pass.
+struct SlabOp {
+    int pass;  // 1 or 2
+    int z0, nz;
+};
+std::vector<SlabOp> slab_schedule(const StepKey &k, const Member &m);
+
 bool node_two_pass(const StepKey &k, NodeLaunch *dens_node,
                    NodeLaunch *step_node, const Member &m);
 bool node_fused(const StepKey &k, const int *tile, NodeLaunch *node,

@@ -17,6 +17,7 @@
 // the stencil's concentration pairs and stores f*.  Per site it moves 2Q reads
 // + 2Q writes of populations plus 24 B of moments each way (FP32), instead of
 // 4Q reads + 2Q writes.
+#include <algorithm>
 #include <type_traits>
 
 #include "fused_impl.h"  // FusedGeom, lds_force, halo_pos, xcd_remap
@@ -302,7 +303,7 @@ __global__ void __launch_bounds__(256)
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
-    if (x < m.nx && y < m.ny) moments_site_buf<ST>(m, sb, mom, x, y, blockIdx.z);
+    if (x < m.nx && y < m.ny) moments_site_buf<ST>(m, sb, mom, x, y, m.zoff + blockIdx.z);
 }
 
 template <int ORDER, class ST, int PSI>
@@ -314,7 +315,7 @@ __global__ void __launch_bounds__(256)
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
     if (x < m.nx && y < m.ny)
-        collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, blockIdx.z);
+        collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, m.zoff + blockIdx.z);
 }
 
 template <class ST>
@@ -513,6 +514,38 @@ static void mom_blocks(const Member &m, bool lds, dim3 *gm, dim3 *bm, dim3 *gc,
     }
 }
 
+// Slabs of at least the stencil's z-radius planes and about kSlabMomentBytes
+// of moments each, for lattices with more than kSlabMinMomentBytes of moments
+// (24 B per site in FP32); stochastic rounding keeps whole launches (its step
+// counter advances at the first block of pass 1).  Order, n slabs:
+// P1(n-1), P1(0), then P1(k+1), P2(k) for k = 0..n-2, then P2(n-1): pass 2 of
+// slab k needs the moments of slabs k-1..k+1, and pass 1 only reads the
+// source buffer, which no pass 2 writes.
+static constexpr size_t kSlabMomentBytes = (size_t)12 << 20;
+static constexpr size_t kSlabMinMomentBytes = (size_t)64 << 20;
+
+std::vector<SlabOp> slab_schedule(const StepKey &k, const Member &m) {
+    std::vector<SlabOp> ops;
+    if (k.dim != 3 || k.storage == ST_F64 || k.mom != 1 || k.big || m.sr) return ops;
+    const size_t plane = (size_t)6 * 4 * m.nx * m.ny;
+    if (plane * m.nz <= kSlabMinMomentBytes) return ops;
+    const int rz = k.order == 4 ? 1 : 2;
+    const int per = std::max(rz, (int)(kSlabMomentBytes / plane));
+    const int n = (m.nz + per - 1) / per;
+    if (n < 3 || m.nz / n < rz) return ops;
+    std::vector<int> z0(n + 1, 0);
+    for (int i = 0; i < n; ++i) z0[i + 1] = z0[i] + m.nz / n + (i < m.nz % n ? 1 : 0);
+    auto op = [&](int pass, int i) { ops.push_back({pass, z0[i], z0[i + 1] - z0[i]}); };
+    op(1, n - 1);
+    op(1, 0);
+    for (int i = 0; i + 1 < n; ++i) {
+        if (i + 1 != n - 1) op(1, i + 1);
+        op(2, i);
+    }
+    op(2, n - 1);
+    return ops;
+}
+
 hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
                            void *dst, void *dens, hipStream_t st) {
     hipError_t err = hipErrorInvalidValue;
@@ -527,7 +560,23 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
             const dim3 g = tp_grid(m), b(TP_BX, TP_BY, 1);
             bool done = false;
             if constexpr (buf_form<D, ST>()) {
-                if (k.mom && !k.big) {
+                const std::vector<SlabOp> slabs = slab_schedule(k, m);
+                if (!slabs.empty()) {
+                    dim3 gm, bm, gc, bc;
+                    mom_blocks(m, false, &gm, &bm, &gc, &bc);
+                    for (const SlabOp &o : slabs) {
+                        Member ms = m;
+                        ms.zoff = o.z0;
+                        gm.z = gc.z = o.nz;
+                        if (o.pass == 1)
+                            hipLaunchKernelGGL((k_moments_buf<ST>), gm, bm, 0, st, ms,
+                                               (const T *)src, (R *)dens);
+                        else
+                            hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P>), gc, bc, 0, st, ms,
+                                               (const T *)src, (T *)dst, (const R *)dens);
+                    }
+                    done = true;
+                } else if (k.mom && !k.big) {
                     dim3 gm, bm, gc, bc;
                     mom_blocks(m, k.mom == 2, &gm, &bm, &gc, &bc);
                     hipLaunchKernelGGL((k_moments_buf<ST>), gm, bm, 0, st, m,
