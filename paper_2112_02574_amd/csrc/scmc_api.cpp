@@ -305,6 +305,7 @@ Member member_of(const scmc_problem &p) {
     m.nx = p.nx;
     m.ny = p.ny;
     m.nz = p.nz;
+    m.znum = p.nz;
     m.N = p.nx * p.ny * p.nz;
     m.pop_off = 0;
     m.dens_off = 0;
@@ -761,9 +762,10 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
             if (!slabs.empty()) {  // the moment two-pass in z-slabs, as launch_two_pass
                 for (const SlabOp &o : slabs) {
                     NodeLaunch nl = o.pass == 1 ? dn : sn;
-                    nl.grid.z = o.nz;
+                    nl.grid = dim3(linear_blocks(m, o.nz));
                     mv = m;
                     mv.zoff = o.z0;
+                    mv.znum = o.nz;
                     if (!rc) rc = add(nl, o.pass == 1 ? dargs : sargs);
                 }
                 continue;

@@ -27,7 +27,8 @@ struct Member {
     unsigned seed;    // its seed
     unsigned *step_ctr;  // device step counter: advanced by the first pass of
                          // a two-pass step, read by the second (random stream)
-    int zoff;            // first z-plane of a slab launch (moment two-pass)
+    int zoff, znum;      // z-planes [zoff, zoff + znum) of a launch of the
+                         // moment two-pass (the whole lattice: 0, nz)
 };
 
 // A unit of work of the batched launches: member index and tile origin.
@@ -83,6 +84,8 @@ struct SlabOp {
     int z0, nz;
 };
 std::vector<SlabOp> slab_schedule(const StepKey &k, const Member &m);
+// Blocks of 256 sites that cover znum planes of m.
+int linear_blocks(const Member &m, int znum);
 
 bool node_two_pass(const StepKey &k, NodeLaunch *dens_node,
                    NodeLaunch *step_node, const Member &m);

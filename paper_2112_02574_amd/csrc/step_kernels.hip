@@ -295,15 +295,28 @@ __global__ void __launch_bounds__(TX *TY)
     }
 }
 
+// The moment two-pass over one lattice numbers its sites linearly: block b
+// takes the 256 consecutive sites from plane zoff on, so no lane idles
+// whatever the row length.  False past plane zoff + znum.
+__device__ __forceinline__ bool linear_site(const Member &m, int &x, int &y, int &z) {
+    const int nxy = m.nx * m.ny;
+    const int s = m.zoff * nxy + blockIdx.x * 256 + threadIdx.x;
+    if (s >= (m.zoff + m.znum) * nxy) return false;
+    z = s / nxy;
+    const int r = s - z * nxy;
+    y = r / m.nx;
+    x = r - y * m.nx;
+    return true;
+}
+
 template <class ST>
 __global__ void __launch_bounds__(256)
     k_moments_buf(Member m, const typename ST::T *__restrict__ src,
                   typename ST::R *__restrict__ mom) {
-    advance_step_counter(m, blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    advance_step_counter(m, blockIdx.x == 0);
     const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
-    if (x < m.nx && y < m.ny) moments_site_buf<ST>(m, sb, mom, x, y, m.zoff + blockIdx.z);
+    int x, y, z;
+    if (linear_site(m, x, y, z)) moments_site_buf<ST>(m, sb, mom, x, y, z);
 }
 
 template <int ORDER, class ST, int PSI>
@@ -311,11 +324,9 @@ __global__ void __launch_bounds__(256)
     k_collide_mom_buf(Member m, const typename ST::T *__restrict__ src,
                       typename ST::T *__restrict__ dst,
                       const typename ST::R *__restrict__ mom) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
-    if (x < m.nx && y < m.ny)
-        collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, m.zoff + blockIdx.z);
+    int x, y, z;
+    if (linear_site(m, x, y, z)) collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, z);
 }
 
 template <class ST>
@@ -497,20 +508,23 @@ static dim3 tp_grid(const Member &m) {
 // (StepKey::mom == 2) marches 64 x 8 columns through z-chunks of 8 planes.
 constexpr int CL_TX = 64, CL_TY = 8, CL_ZC = 8;
 
+int linear_blocks(const Member &m, int znum) {
+    return (int)(((long)znum * m.nx * m.ny + 255) / 256);
+}
+
+// Launch shapes of the moment two-pass: 256 linearly numbered sites per block
+// (linear_site), or the LDS-staged pass 2.
 static void mom_blocks(const Member &m, bool lds, dim3 *gm, dim3 *bm, dim3 *gc,
                        dim3 *bc) {
-    *bm = dim3(64, 1, 1);
-    *gm = dim3((m.nx + 63) / 64, m.ny, m.nz);
+    *bm = dim3(256, 1, 1);
+    *gm = dim3(linear_blocks(m, m.znum));
     if (lds) {
         const int ntx = (m.nx + CL_TX - 1) / CL_TX, nty = (m.ny + CL_TY - 1) / CL_TY;
         *bc = dim3(CL_TX, CL_TY, 1);
         *gc = dim3(ntx * nty * ((m.nz + CL_ZC - 1) / CL_ZC), 1, 1);
-    } else if (m.nx >= 128) {  // direct gathers: 128 x 2 blocks on long rows
-        *bc = dim3(128, 2, 1);
-        *gc = dim3((m.nx + 127) / 128, (m.ny + 1) / 2, m.nz);
     } else {
-        *bc = dim3(TP_BX, TP_BY, 1);
-        *gc = tp_grid(m);
+        *bc = *bm;
+        *gc = *gm;
     }
 }
 
@@ -567,7 +581,8 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
                     for (const SlabOp &o : slabs) {
                         Member ms = m;
                         ms.zoff = o.z0;
-                        gm.z = gc.z = o.nz;
+                        ms.znum = o.nz;
+                        gm = gc = dim3(linear_blocks(m, o.nz));
                         if (o.pass == 1)
                             hipLaunchKernelGGL((k_moments_buf<ST>), gm, bm, 0, st, ms,
                                                (const T *)src, (R *)dens);
