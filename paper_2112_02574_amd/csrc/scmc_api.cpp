@@ -762,7 +762,7 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
             if (!slabs.empty()) {  // the moment two-pass in z-slabs, as launch_two_pass
                 for (const SlabOp &o : slabs) {
                     NodeLaunch nl = o.pass == 1 ? dn : sn;
-                    nl.grid = dim3(linear_blocks(m, o.nz));
+                    nl.grid = dim3(linear_blocks(m, o.nz, (int)nl.block.x));
                     mv = m;
                     mv.zoff = o.z0;
                     mv.znum = o.nz;

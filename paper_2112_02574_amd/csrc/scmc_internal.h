@@ -84,8 +84,8 @@ struct SlabOp {
     int z0, nz;
 };
 std::vector<SlabOp> slab_schedule(const StepKey &k, const Member &m);
-// Blocks of 256 sites that cover znum planes of m.
-int linear_blocks(const Member &m, int znum);
+// Blocks of blk linearly numbered sites that cover znum planes of m.
+int linear_blocks(const Member &m, int znum, int blk);
 
 bool node_two_pass(const StepKey &k, NodeLaunch *dens_node,
                    NodeLaunch *step_node, const Member &m);

@@ -296,11 +296,15 @@ __global__ void __launch_bounds__(TX *TY)
 }
 
 // The moment two-pass over one lattice numbers its sites linearly: block b
-// takes the 256 consecutive sites from plane zoff on, so no lane idles
-// whatever the row length.  False past plane zoff + znum.
+// takes the BLK consecutive sites from plane zoff on, so no lane idles
+// whatever the row length.  False past plane zoff + znum.  Blocks of 256
+// sites suit lattices whose moment field stays cached; the z-slab schedule
+// of larger lattices runs blocks of 512 (SLAB_BLOCK).
+constexpr int LIN_BLOCK = 256, SLAB_BLOCK = 512;
+template <int BLK>
 __device__ __forceinline__ bool linear_site(const Member &m, int &x, int &y, int &z) {
     const int nxy = m.nx * m.ny;
-    const int s = m.zoff * nxy + blockIdx.x * 256 + threadIdx.x;
+    const int s = m.zoff * nxy + blockIdx.x * BLK + threadIdx.x;
     if (s >= (m.zoff + m.znum) * nxy) return false;
     z = s / nxy;
     const int r = s - z * nxy;
@@ -309,24 +313,24 @@ __device__ __forceinline__ bool linear_site(const Member &m, int &x, int &y, int
     return true;
 }
 
-template <class ST>
-__global__ void __launch_bounds__(256)
+template <class ST, int BLK>
+__global__ void __launch_bounds__(BLK)
     k_moments_buf(Member m, const typename ST::T *__restrict__ src,
                   typename ST::R *__restrict__ mom) {
     advance_step_counter(m, blockIdx.x == 0);
     const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
     int x, y, z;
-    if (linear_site(m, x, y, z)) moments_site_buf<ST>(m, sb, mom, x, y, z);
+    if (linear_site<BLK>(m, x, y, z)) moments_site_buf<ST>(m, sb, mom, x, y, z);
 }
 
-template <int ORDER, class ST, int PSI>
-__global__ void __launch_bounds__(256)
+template <int ORDER, class ST, int PSI, int BLK>
+__global__ void __launch_bounds__(BLK)
     k_collide_mom_buf(Member m, const typename ST::T *__restrict__ src,
                       typename ST::T *__restrict__ dst,
                       const typename ST::R *__restrict__ mom) {
     const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
     int x, y, z;
-    if (linear_site(m, x, y, z)) collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, z);
+    if (linear_site<BLK>(m, x, y, z)) collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, z);
 }
 
 template <class ST>
@@ -508,16 +512,16 @@ static dim3 tp_grid(const Member &m) {
 // (StepKey::mom == 2) marches 64 x 8 columns through z-chunks of 8 planes.
 constexpr int CL_TX = 64, CL_TY = 8, CL_ZC = 8;
 
-int linear_blocks(const Member &m, int znum) {
-    return (int)(((long)znum * m.nx * m.ny + 255) / 256);
+int linear_blocks(const Member &m, int znum, int blk) {
+    return (int)(((long)znum * m.nx * m.ny + blk - 1) / blk);
 }
 
 // Launch shapes of the moment two-pass: 256 linearly numbered sites per block
 // (linear_site), or the LDS-staged pass 2.
 static void mom_blocks(const Member &m, bool lds, dim3 *gm, dim3 *bm, dim3 *gc,
                        dim3 *bc) {
-    *bm = dim3(256, 1, 1);
-    *gm = dim3(linear_blocks(m, m.znum));
+    *bm = dim3(LIN_BLOCK, 1, 1);
+    *gm = dim3(linear_blocks(m, m.znum, LIN_BLOCK));
     if (lds) {
         const int ntx = (m.nx + CL_TX - 1) / CL_TX, nty = (m.ny + CL_TY - 1) / CL_TY;
         *bc = dim3(CL_TX, CL_TY, 1);
@@ -576,32 +580,32 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
             if constexpr (buf_form<D, ST>()) {
                 const std::vector<SlabOp> slabs = slab_schedule(k, m);
                 if (!slabs.empty()) {
-                    dim3 gm, bm, gc, bc;
-                    mom_blocks(m, false, &gm, &bm, &gc, &bc);
+                    const dim3 b(SLAB_BLOCK, 1, 1);
                     for (const SlabOp &o : slabs) {
                         Member ms = m;
                         ms.zoff = o.z0;
                         ms.znum = o.nz;
-                        gm = gc = dim3(linear_blocks(m, o.nz));
+                        const dim3 g(linear_blocks(m, o.nz, SLAB_BLOCK));
                         if (o.pass == 1)
-                            hipLaunchKernelGGL((k_moments_buf<ST>), gm, bm, 0, st, ms,
+                            hipLaunchKernelGGL((k_moments_buf<ST, SLAB_BLOCK>), g, b, 0, st, ms,
                                                (const T *)src, (R *)dens);
                         else
-                            hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P>), gc, bc, 0, st, ms,
-                                               (const T *)src, (T *)dst, (const R *)dens);
+                            hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P, SLAB_BLOCK>), g, b, 0,
+                                               st, ms, (const T *)src, (T *)dst,
+                                               (const R *)dens);
                     }
                     done = true;
                 } else if (k.mom && !k.big) {
                     dim3 gm, bm, gc, bc;
                     mom_blocks(m, k.mom == 2, &gm, &bm, &gc, &bc);
-                    hipLaunchKernelGGL((k_moments_buf<ST>), gm, bm, 0, st, m,
+                    hipLaunchKernelGGL((k_moments_buf<ST, LIN_BLOCK>), gm, bm, 0, st, m,
                                        (const T *)src, (R *)dens);
                     if (k.mom == 2)
                         hipLaunchKernelGGL((k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P>),
                                            gc, bc, 0, st, m, (const T *)src, (T *)dst,
                                            (const R *)dens);
                     else
-                        hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P>), gc, bc, 0, st, m,
+                        hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P, LIN_BLOCK>), gc, bc, 0, st, m,
                                            (const T *)src, (T *)dst, (const R *)dens);
                     done = true;
                 }
@@ -641,11 +645,16 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dn, NodeLaunch *sn,
             dn->shmem = sn->shmem = 0;
             if constexpr (buf_form<D, ST>()) {
                 if (k.mom && !k.big) {
-                    dn->func = (void *)&k_moments_buf<ST>;
+                    dn->func = (void *)&k_moments_buf<ST, LIN_BLOCK>;
                     sn->func = k.mom == 2
                                    ? (void *)&k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P>
-                                   : (void *)&k_collide_mom_buf<O, ST, P>;
+                                   : (void *)&k_collide_mom_buf<O, ST, P, LIN_BLOCK>;
                     mom_blocks(m, k.mom == 2, &dn->grid, &dn->block, &sn->grid, &sn->block);
+                    if (!slab_schedule(k, m).empty()) {  // slab launches: grid set per slab
+                        dn->func = (void *)&k_moments_buf<ST, SLAB_BLOCK>;
+                        sn->func = (void *)&k_collide_mom_buf<O, ST, P, SLAB_BLOCK>;
+                        dn->block = sn->block = dim3(SLAB_BLOCK, 1, 1);
+                    }
                 }
             }
             ok = true;
