@@ -42,16 +42,32 @@ __device__ __forceinline__ bool tile_site(const Member &m, const Tile &tl, int &
     return true;
 }
 
+// The two-pass designs over one lattice number their sites linearly: block b
+// takes the BLK consecutive sites from plane zoff on, so no lane idles
+// whatever the row length.  False past plane zoff + znum.  Blocks of 256
+// sites suit lattices whose moment field stays cached; the z-slab schedule
+// of larger lattices runs blocks of 512 (SLAB_BLOCK).
+constexpr int LIN_BLOCK = 256, SLAB_BLOCK = 512;
+template <int BLK>
+__device__ __forceinline__ bool linear_site(const Member &m, int &x, int &y, int &z) {
+    const int nxy = m.nx * m.ny;
+    const int s = m.zoff * nxy + blockIdx.x * BLK + threadIdx.x;
+    if (s >= (m.zoff + m.znum) * nxy) return false;
+    z = s / nxy;
+    const int r = s - z * nxy;
+    y = r / m.nx;
+    x = r - y * m.nx;
+    return true;
+}
+
 template <int D, class ST>
 __global__ void __launch_bounds__(256)
     k_density(Member m, const typename ST::T *__restrict__ src,
               typename ST::R *__restrict__ dens) {
     using R = typename ST::R;
-    advance_step_counter(m, blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
-    const int x = blockIdx.x * TP_BX + threadIdx.x;
-    const int y = blockIdx.y * TP_BY + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= m.nx || y >= m.ny) return;
+    advance_step_counter(m, blockIdx.x == 0);
+    int x, y, z;
+    if (!linear_site<LIN_BLOCK>(m, x, y, z)) return;
     R f[2][Lattice<D>::Q];
     pull_site<D, ST>(m, src, x, y, z, f);
     R nA, nB;
@@ -67,10 +83,8 @@ __global__ void __launch_bounds__(256)
               typename ST::T *__restrict__ dst,
               const typename ST::R *__restrict__ dens) {
     using R = typename ST::R;
-    const int x = blockIdx.x * TP_BX + threadIdx.x;
-    const int y = blockIdx.y * TP_BY + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= m.nx || y >= m.ny) return;
+    int x, y, z;
+    if (!linear_site<LIN_BLOCK>(m, x, y, z)) return;
     R f[2][Lattice<D>::Q];
     pull_site<D, ST>(m, src, x, y, z, f);
     R nA, nB;
@@ -295,24 +309,6 @@ __global__ void __launch_bounds__(TX *TY)
     }
 }
 
-// The moment two-pass over one lattice numbers its sites linearly: block b
-// takes the BLK consecutive sites from plane zoff on, so no lane idles
-// whatever the row length.  False past plane zoff + znum.  Blocks of 256
-// sites suit lattices whose moment field stays cached; the z-slab schedule
-// of larger lattices runs blocks of 512 (SLAB_BLOCK).
-constexpr int LIN_BLOCK = 256, SLAB_BLOCK = 512;
-template <int BLK>
-__device__ __forceinline__ bool linear_site(const Member &m, int &x, int &y, int &z) {
-    const int nxy = m.nx * m.ny;
-    const int s = m.zoff * nxy + blockIdx.x * BLK + threadIdx.x;
-    if (s >= (m.zoff + m.znum) * nxy) return false;
-    z = s / nxy;
-    const int r = s - z * nxy;
-    y = r / m.nx;
-    x = r - y * m.nx;
-    return true;
-}
-
 template <class ST, int BLK>
 __global__ void __launch_bounds__(BLK)
     k_moments_buf(Member m, const typename ST::T *__restrict__ src,
@@ -367,10 +363,9 @@ template <int D, class ST>
 __global__ void __launch_bounds__(256)
     k_moments(Member m, const typename ST::T *__restrict__ src,
               typename ST::R *__restrict__ mom) {
-    advance_step_counter(m, blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
-    const int x = blockIdx.x * TP_BX + threadIdx.x;
-    const int y = blockIdx.y * TP_BY + threadIdx.y;
-    if (x < m.nx && y < m.ny) moments_site<D, ST>(m, src, mom, x, y, blockIdx.z);
+    advance_step_counter(m, blockIdx.x == 0);
+    int x, y, z;
+    if (linear_site<LIN_BLOCK>(m, x, y, z)) moments_site<D, ST>(m, src, mom, x, y, z);
 }
 
 template <int D, int ORDER, class ST, int PSI>
@@ -378,10 +373,8 @@ __global__ void __launch_bounds__(256)
     k_collide_mom(Member m, const typename ST::T *__restrict__ src,
                   typename ST::T *__restrict__ dst,
                   const typename ST::R *__restrict__ mom) {
-    const int x = blockIdx.x * TP_BX + threadIdx.x;
-    const int y = blockIdx.y * TP_BY + threadIdx.y;
-    if (x < m.nx && y < m.ny)
-        collide_mom_site<D, ORDER, ST, PSI>(m, dst, mom, x, y, blockIdx.z);
+    int x, y, z;
+    if (linear_site<LIN_BLOCK>(m, x, y, z)) collide_mom_site<D, ORDER, ST, PSI>(m, dst, mom, x, y, z);
 }
 
 template <int D, class ST>
@@ -503,13 +496,8 @@ template <int D, class ST> constexpr bool buf_form() {
     return D == 3 && !std::is_same<ST, StoreF64>::value;
 }
 
-static dim3 tp_grid(const Member &m) {
-    return dim3((m.nx + TP_BX - 1) / TP_BX, (m.ny + TP_BY - 1) / TP_BY, m.nz);
-}
-
-// Launch shapes of the buffer-form moment passes (measured on 128^3): one
-// 64-wide row per block for the pull pass; the LDS-staged collision pass
-// (StepKey::mom == 2) marches 64 x 8 columns through z-chunks of 8 planes.
+// The LDS-staged collision pass (StepKey::mom == 2) marches 64 x 8 columns
+// through z-chunks of 8 planes (measured on 128^3).
 constexpr int CL_TX = 64, CL_TY = 8, CL_ZC = 8;
 
 int linear_blocks(const Member &m, int znum, int blk) {
@@ -575,7 +563,7 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
             constexpr int D = decltype(Dc)::value;
             constexpr int O = decltype(Oc)::value;
             constexpr int P = decltype(Pc)::value;
-            const dim3 g = tp_grid(m), b(TP_BX, TP_BY, 1);
+            const dim3 g(linear_blocks(m, m.znum, LIN_BLOCK)), b(LIN_BLOCK, 1, 1);
             bool done = false;
             if constexpr (buf_form<D, ST>()) {
                 const std::vector<SlabOp> slabs = slab_schedule(k, m);
@@ -640,8 +628,8 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dn, NodeLaunch *sn,
             dn->func = k.mom ? (void *)&k_moments<D, ST> : (void *)&k_density<D, ST>;
             sn->func = k.mom ? (void *)&k_collide_mom<D, O, ST, P>
                              : (void *)&k_collide<D, O, ST, P>;
-            dn->grid = sn->grid = tp_grid(m);
-            dn->block = sn->block = dim3(TP_BX, TP_BY, 1);
+            dn->grid = sn->grid = dim3(linear_blocks(m, m.znum, LIN_BLOCK));
+            dn->block = sn->block = dim3(LIN_BLOCK, 1, 1);
             dn->shmem = sn->shmem = 0;
             if constexpr (buf_form<D, ST>()) {
                 if (k.mom && !k.big) {
