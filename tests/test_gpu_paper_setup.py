@@ -121,3 +121,37 @@ def test_tolman_length_changes_sign_with_asymmetry():
     assert -0.6 < deltas[0.88] < -0.15
     assert 0.3 < deltas[-0.88] < 1.0
     assert abs(deltas[-0.88]) > abs(deltas[0.88])
+
+
+@pytest.mark.parametrize("storage,tol_n,tol_p,tol_r", [(scmc.F64, 1e-10, 1e-10, 1e-8),
+                                                      (scmc.F32, 2e-5, 1e-4, 1e-3)])
+def test_asymmetric_paper_droplet_matches_oracle(storage, tol_n, tol_p, tol_r):
+    """The paper's asymmetric set (dG_AB = +0.88: psi = exp(-1/n), E4, g_AA
+    from eq. self_p) on an odd box, a B-rich droplet run 2048 steps on the
+    GPU and in the FP64 oracle from the same fields: concentrations, Delta P,
+    R_s and sigma_s agree (FP64 to rounding; FP32 to its storage precision:
+    2e-5 in n, 1e-4 relative in Delta P, 1e-3 relative in R_s and sigma_s)."""
+    from oracle import oracle as O
+    L, R0 = 23, 23 / 4
+    g = _couplings(0.88)
+    bulk = (1.689083, 0.075715, 0.019165, 2.613069)  # flat-stage values of this set
+    nA, nB = inputs.droplet(L, L, L, R=R0, a_rich=False, bulk=bulk)
+    s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E4, (L, L, L), g=g,
+                              psi_self=scmc.PSI_EXP_NEG_INV, storage=storage,
+                              n0=(0.5 * (bulk[0] + bulk[2]), 0.5 * (bulk[1] + bulk[3]))))
+    s.scmc_set_density(nA, nB)
+    s.scmc_step(2048)
+    n = s.scmc_get_fields()
+    o_gpu = s.scmc_observables(scmc.OBS_DROPLET, R0)
+    s.close()
+    o = O.Oracle(3, 4, (L, L, L), g=g, psi_self=O.PSI_EXP)
+    o.set_density(nA, nB)
+    o.run(2048)
+    ob = o.droplet_observables(R0)
+    print(f"storage {storage}: dP {o_gpu['dP']:.10g} ({ob['dP']:.10g}) R_s {o_gpu['R_s']:.8g} "
+          f"({ob['R_s']:.8g})", flush=True)
+    assert np.abs(n - o.density()).max() < tol_n
+    assert abs(o_gpu["dP"] - ob["dP"]) < tol_p * abs(ob["dP"])
+    # R_s and sigma_s inherit the cancellation in C_d: relative bounds tol_r
+    assert abs(o_gpu["R_s"] - ob["R_s"]) < tol_r * ob["R_s"]
+    assert abs(o_gpu["sigma_s"] - ob["sigma_s"]) < tol_r * ob["sigma_s"]
