@@ -321,7 +321,13 @@ def test_full_size_sampled_single_step():
     sim.close()
 
 
-def test_slab_pipelined_moment_pass_single_step():
+_GC = -np.e ** 2 / 3.0
+
+
+@pytest.mark.parametrize("stencil,psi,g", [
+    (scmc.E6, scmc.PSI_N, ((0.0, 1.8), (1.8, 0.0))),
+    (scmc.E4, scmc.PSI_EXP_NEG_INV, ((_GC * 0.6, 0.5), (0.5, _GC * 0.6)))])
+def test_slab_pipelined_moment_pass_single_step(stencil, psi, g):
     """A lattice whose moment field (85 MB) exceeds the slab threshold runs the
     moment two-pass in z-slabs (seven of 13-14 planes), pass 2 of each slab
     after pass 1 of the next.  One step from a droplet against the oracle
@@ -329,12 +335,14 @@ def test_slab_pipelined_moment_pass_single_step():
     on the interface and in the bulk."""
     nz, ny, nx, R0 = 96, 192, 192, 30.0
     nA, nB = inputs.droplet(nx, ny, nz, R=R0)
-    sim = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (nz, ny, nx), storage=scmc.F32))
+    sim = scmc.Sim(scmc.problem(scmc.D3Q19, stencil, (nz, ny, nx), g=g, psi_self=psi,
+                                storage=scmc.F32))
     sim.scmc_set_density(nA, nB)
     sim.scmc_step(1)
     f1, _ = sim.scmc_get_populations()
     sim.close()
-    o = O.Oracle(3, 6, (nz, ny, nx))
+    o = O.Oracle(3, stencil, (nz, ny, nx), g=g,
+                 psi_self=O.PSI_EXP if psi == scmc.PSI_EXP_NEG_INV else O.PSI_N)
     o.set_density(nA, nB)
     xi, _ = scmc.velocities(scmc.D3Q19)
     perm = _perm(scmc.D3Q19, 3)
