@@ -72,7 +72,10 @@ typedef enum {
     SCMC_BF16_OFF = 3 /* same with bfloat16 */
 } scmc_storage;
 typedef enum {
-    SCMC_KERNEL_AUTO = 0,        /* fused when available, else two-pass */
+    SCMC_KERNEL_AUTO = 0,        /* tau_A = tau_B = 1: TWO_PASS_MOM; otherwise
+                                    FUSED where it exists (D3Q19, E4/E6,
+                                    FP32/FP16/BF16), else TWO_PASS;
+                                    scmc_autotune may choose another */
     SCMC_KERNEL_TWO_PASS = 1,    /* density pass + stream/force/collide pass */
     SCMC_KERNEL_FUSED = 2,       /* one z-marching kernel per step (D3Q19 with
                                     E4/E6, FP32/FP16/BF16 storage); the pulled
@@ -86,15 +89,16 @@ typedef enum {
                                      then depends on the pulled populations
                                      only through n_J and the total momentum,
                                      so five moments per node wait in
-                                     registers instead of 2Q populations;
-                                     the default when tau = 1 */
+                                     registers instead of 2Q populations */
     SCMC_KERNEL_FUSED_MOM_PIPE = 6, /* the same with the next plane's loads
                                        issued early (tau = 1 only) */
     SCMC_KERNEL_TWO_PASS_MOM = 7  /* two passes for tau = 1 only: the first
                                      pulls and stores n_J and the momentum,
                                      the second collides from those moments
                                      without pulling again (every lattice,
-                                     stencil and storage); with a nonzero
+                                     stencil and storage; lattices with more
+                                     than 64 MB of moments run it in
+                                     z-slabs); with a nonzero
                                      tile (D3Q19, FP32/FP16/BF16) the second
                                      pass stages the stencil's concentrations
                                      in LDS (64 x 8 columns, z-chunks of 8) */
