@@ -193,8 +193,9 @@ def _timed(step, steps, stream):
 
 
 def variants(args, L, R0, bulk, init, dev, stream):
-    """Step rates of the other storage formats on the same droplet, and of the
-    48-member batched sweep, each over ``args.variant_steps`` timed steps."""
+    """Step rates of the other storage formats on the same droplet, of the
+    same droplet doubled in size (256^3), and of the 48-member batched sweep,
+    each over ``args.variant_steps`` timed steps."""
     from paper_2112_02574_amd import inputs
     from paper_2112_02574_amd import scmc
     N = L ** 3
@@ -214,6 +215,20 @@ def variants(args, L, R0, bulk, init, dev, stream):
                      "tile": list(tile), "bytes_per_site": 4 * 19 * size,
                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
         s.close()
+    # a lattice whose moment field outgrows the caches: the 256^3 droplet
+    # (R0 = 64) in FP32 with the tuned design (the z-slab moment two-pass)
+    Lb = 2 * L
+    s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (Lb, Lb, Lb), g=G_SYM, storage=scmc.F32),
+                 device=dev, stream=stream)
+    s.scmc_autotune(args.tune_cache)
+    s.scmc_set_density(*inputs.droplet(Lb, Lb, Lb, R=2 * R0, bulk=bulk))
+    ms = _timed(s.scmc_step, args.variant_steps, stream)
+    kernel, tile = s.scmc_config()
+    Nb = Lb ** 3
+    out[f"f32_{Lb}cube"] = {"MLUPS": round(Nb / (ms * 1e3), 1), "kernel": KERNEL_NAMES[kernel],
+                            "tile": list(tile), "bytes_per_site": 304,
+                            "hbm_frac": round(304 * Nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    s.close()
     # the batched sweep: 48 droplets on 48^3..160^3 boxes, symmetric and
     # asymmetric couplings, FP32, one persistent launch per step
     members = inputs.batch_members()
