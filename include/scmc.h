@@ -178,11 +178,19 @@ typedef struct scmc_sim scmc_sim;
  * On failure *out is NULL. */
 int scmc_create(const scmc_problem *p, void *d_ws, size_t ws_bytes,
                 void *stream, scmc_sim **out);
+/* Waits for the work queued on the handle's stream (so the caller may reuse
+ * the workspace as soon as this returns), then frees the handle; SCMC_EDEVICE
+ * if that wait reports a HIP error (the handle is freed anyway). */
 int scmc_destroy(scmc_sim *s);
 
 /* f_i^J(x, 0) = w_i n_J(x) (zero velocity; the paper does not state the
  * initial populations), t = 0.  nA, nB: N host doubles each.  EINVAL on a
- * non-finite value. */
+ * non-finite value.
+ * Device state: after scmc_set_density or scmc_set_populations, and until the
+ * next step, the state is the first 2*Q*N values of the storage type at the
+ * start of the workspace, laid out [J][i][z][y][x]; value (J, i, x) is the
+ * post-collision f*_i^J(x) that the next step streams to x + xi_i (FP16 /
+ * BF16: the offset f* - w_i n0_J). */
 int scmc_set_density(scmc_sim *s, const double *nA, const double *nB);
 
 /* Advance nsteps >= 0 time steps, asynchronously.  With graph steps k > 0
@@ -276,13 +284,16 @@ typedef struct scmc_batch scmc_batch;
 int scmc_batch_workspace_bytes(const scmc_problem *ps, int count, size_t *out);
 int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
                       size_t ws_bytes, void *stream, scmc_batch **out);
-int scmc_batch_destroy(scmc_batch *b);
+int scmc_batch_destroy(scmc_batch *b);  /* waits for the stream, as scmc_destroy */
 int scmc_batch_set_density(scmc_batch *b, int i, const double *nA,
                            const double *nB);
 int scmc_batch_step(scmc_batch *b, int64_t nsteps);
 int scmc_batch_set_graph_steps(scmc_batch *b, int k);
 int scmc_batch_get_fields(scmc_batch *b, int i, double *nA, double *nB,
                           double *u);
+/* Member i's pre-collision populations f[2*Q*N_i] (layout as
+ * scmc_get_populations) and the batch's step.  Synchronous. */
+int scmc_batch_get_populations(scmc_batch *b, int i, double *f, int64_t *step);
 int scmc_batch_stats_get(scmc_batch *b, int i, scmc_stats *out);
 int scmc_batch_observables(scmc_batch *b, int i, int kind, double R0,
                            scmc_obs *out, double *PN, double *PT);

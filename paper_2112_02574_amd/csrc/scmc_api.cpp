@@ -884,9 +884,12 @@ int scmc_create(const scmc_problem *p, void *d_ws, size_t ws_bytes,
 
 int scmc_destroy(scmc_sim *s) {
     if (!s) return SCMC_EINVAL;
+    // queued steps still write the caller's workspace: let them finish before
+    // the caller may reuse that memory
+    const hipError_t e = hipStreamSynchronize(s->c.stream);
     drop_graphs(s->c);
     delete s;
-    return SCMC_OK;
+    return e == hipSuccess ? SCMC_OK : SCMC_EDEVICE;
 }
 
 int scmc_set_density(scmc_sim *s, const double *nA, const double *nB) {
@@ -1356,9 +1359,10 @@ int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
 
 int scmc_batch_destroy(scmc_batch *b) {
     if (!b) return SCMC_EINVAL;
+    const hipError_t e = hipStreamSynchronize(b->c.stream);  // as scmc_destroy
     drop_graphs(b->c);
     delete b;
-    return SCMC_OK;
+    return e == hipSuccess ? SCMC_OK : SCMC_EDEVICE;
 }
 
 static const void *member_pop(const scmc_batch *b, int i, int buf) {
@@ -1407,6 +1411,15 @@ int scmc_batch_get_fields(scmc_batch *b, int i, double *nA, double *nB,
     if (!b || i < 0 || i >= (int)b->lats.size()) return SCMC_EINVAL;
     if (!b->c.initialized) return fail(b->c, SCMC_ESTATE, "state not set");
     return fields_impl(b->c, b->lats[i], member_pop(b, i, b->c.cur), nA, nB, u);
+}
+
+int scmc_batch_get_populations(scmc_batch *b, int i, double *f, int64_t *step) {
+    if (!b || !f || i < 0 || i >= (int)b->lats.size()) return SCMC_EINVAL;
+    if (!b->c.initialized) return fail(b->c, SCMC_ESTATE, "state not set");
+    int rc = download_state(b->c, b->lats[i], member_pop(b, i, b->c.cur), f);
+    if (rc) return rc;
+    if (step) *step = b->c.step;
+    return SCMC_OK;
 }
 
 int scmc_batch_stats_get(scmc_batch *b, int i, scmc_stats *out) {

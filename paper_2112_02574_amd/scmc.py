@@ -110,6 +110,8 @@ _SYMBOLS = {
     "scmc_batch_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
     "scmc_batch_set_graph_steps": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "scmc_batch_get_fields": ([ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 3, ctypes.c_int),
+    "scmc_batch_get_populations": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "scmc_batch_stats_get": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Stats)], ctypes.c_int),
     "scmc_batch_observables": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.POINTER(Obs), ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -265,6 +267,9 @@ class Sim:
         self.ws = _device_buffer(scmc_workspace_bytes(p), device)
         with torch.cuda.device(self.ws.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream()
+        # the library queues its kernels on self.stream: tell the caching
+        # allocator, so the workspace is not handed out again while they run
+        self.ws.record_stream(self.stream)
         h = ctypes.c_void_p()
         rc = lib().scmc_create(ctypes.byref(p), ctypes.c_void_p(self.ws.data_ptr()),
                                self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream),
@@ -378,6 +383,7 @@ class Batch:
         self.ws = _device_buffer(need.value, device)
         with torch.cuda.device(self.ws.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ws.record_stream(self.stream)  # as in Sim
         h = ctypes.c_void_p()
         rc = lib().scmc_batch_create(arr, self.count, ctypes.c_void_p(self.ws.data_ptr()),
                                      self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream),
@@ -424,6 +430,15 @@ class Batch:
                     "scmc_batch_get_fields")
         n = np.stack([nA, nB]).reshape((2,) + shp)
         return (n, u.reshape((3,) + shp)) if velocity else n
+
+    def scmc_batch_get_populations(self, i):
+        N, shp = self._n(i)
+        q = 9 if self.problems[i].lattice == D2Q9 else 19
+        f = np.zeros(2 * q * N)
+        step = ctypes.c_int64()
+        self._check(lib().scmc_batch_get_populations(self.h, i, _ptr(f), ctypes.byref(step)),
+                    "scmc_batch_get_populations")
+        return f.reshape((2, q) + shp), step.value
 
     def scmc_batch_stats_get(self, i):
         s = Stats()

@@ -6,6 +6,7 @@ library.  Usage (repository root):
 
     python tests/golden/make_golden.py c1      # 64^2 slab, 2000 steps
     python tests/golden/make_golden.py c2      # 4 x 256^2 droplets, 20000 steps
+    python tests/golden/make_golden.py c2conv  # the same run to the Sec. 4 dP criterion
     python tests/golden/make_golden.py c3      # 128^3 droplet, 30000 steps
 
 Each writes tests/golden/<name>_oracle.json.  The droplet cases start the way
@@ -84,6 +85,36 @@ def c2():
     _write("c2", out)
 
 
+def c2conv(every=2048, tol=1e-5, max_steps=400000):
+    """The four droplets of c2 run on until the Delta P criterion of Sec. 4:
+    |dP(t) - dP(t - 2^11)| / |dP(t - 2^11)| < 1e-5.  Per member: the step at
+    which it holds, the observables there and the dP, R_s history."""
+    bulk, fsteps = flat_bulk(2, 8, G_SYM)
+    out = {"every": every, "tol": tol, "bulk": bulk, "flat_steps": fsteps, "flat_lx": 128,
+           "members": []}
+    for R0 in (12.0, 20.0, 32.0, 48.0):
+        t0 = time.time()
+        o = O.Oracle(2, 8, (256, 256), tau=1.0, g=G_SYM, nthreads=THREADS)
+        o.set_density(*inputs.droplet(256, 256, R=R0, bulk=bulk))
+        hist, done, prev = [], 0, None
+        while done < max_steps:
+            o.run(every)
+            done += every
+            d = o.droplet_observables(R0)
+            hist.append({"step": done, "dP": d["dP"], "R_s": d["R_s"]})
+            change = abs(d["dP"] - prev) / abs(prev) if prev else float("inf")
+            prev = d["dP"]
+            if change < tol:
+                break
+        d = {k: (v.tolist() if hasattr(v, "tolist") else v) for k, v in d.items()}
+        d.update({"R0": R0, "steps": done, "converged": change < tol, "history": hist,
+                  "max_u": o.stats()["max_u"]})
+        out["members"].append(d)
+        print(f"c2conv R0={R0}: {done} steps, dP={d['dP']:.8g} R_s={d['R_s']:.8g} "
+              f"({time.time() - t0:.0f} s)", flush=True)
+    _write("c2conv", out)
+
+
 def c3(steps=30000, every=2048):
     """D3Q19, E6, 128^3 droplet R0 = 24, tau = 1, g_AB = 1.8; observables every
     2048 steps (the paper's monitoring interval) and at the end."""
@@ -114,4 +145,4 @@ def c3(steps=30000, every=2048):
 
 
 if __name__ == "__main__":
-    {"c1": c1, "c2": c2, "c3": c3}[sys.argv[1]]()
+    {"c1": c1, "c2": c2, "c2conv": c2conv, "c3": c3}[sys.argv[1]]()

@@ -39,14 +39,28 @@ def _random_state(shape, seed):
 
 
 CASES = [
-    # lattice, stencil, shape (nz, ny, nx) or (ny, nx), psi, couplings
-    (scmc.D2Q9, scmc.E4, (37, 70), scmc.PSI_N, ((0.0, 1.2), (1.2, 0.0))),
-    (scmc.D2Q9, scmc.E6, (21, 67), scmc.PSI_EXP_NEG_INV, ((-1.0, 0.5), (0.5, -0.6))),
-    (scmc.D2Q9, scmc.E8, (33, 129), scmc.PSI_N, ((-0.1, 1.4), (1.4, 0.05))),
-    (scmc.D3Q19, scmc.E4, (9, 13, 70), scmc.PSI_N, ((0.0, 1.2), (1.2, 0.0))),
-    (scmc.D3Q19, scmc.E6, (11, 7, 67), scmc.PSI_EXP_NEG_INV, ((-1.0, 0.5), (0.5, -0.6))),
-    (scmc.D3Q19, scmc.E6, (6, 9, 130), scmc.PSI_N, ((-0.1, 1.4), (1.4, 0.05))),
+    # lattice, stencil, shape (nz, ny, nx) or (ny, nx), psi, couplings, initial state
+    (scmc.D2Q9, scmc.E4, (37, 70), scmc.PSI_N, ((0.0, 1.2), (1.2, 0.0)), "random"),
+    (scmc.D2Q9, scmc.E6, (21, 67), scmc.PSI_EXP_NEG_INV, ((-1.0, 0.5), (0.5, -0.6)), "random"),
+    (scmc.D2Q9, scmc.E8, (33, 129), scmc.PSI_N, ((-0.1, 1.4), (1.4, 0.05)), "random"),
+    (scmc.D3Q19, scmc.E4, (9, 13, 70), scmc.PSI_N, ((0.0, 1.2), (1.2, 0.0)), "random"),
+    (scmc.D3Q19, scmc.E6, (11, 7, 67), scmc.PSI_EXP_NEG_INV, ((-1.0, 0.5), (0.5, -0.6)), "random"),
+    (scmc.D3Q19, scmc.E6, (6, 9, 130), scmc.PSI_N, ((-0.1, 1.4), (1.4, 0.05)), "random"),
+    # the benchmark's instantiation (E6, psi = n, symmetric g_AB = 1.8) on a
+    # ragged box: a droplet between the bulk values of the flat stage
+    (scmc.D3Q19, scmc.E6, (10, 12, 66), scmc.PSI_N, ((0.0, 1.8), (1.8, 0.0)), "droplet"),
 ]
+
+# designs: (kernel, tile); the moment designs run tau = 1 only, the fused and
+# LDS-staged ones D3Q19 with FP32-compute storage only
+DESIGNS = {
+    "two_pass": (scmc.KERNEL_TWO_PASS, (0, 0, 0)),
+    "auto": (scmc.KERNEL_AUTO, (0, 0, 0)),
+    "two_pass_mom": (scmc.KERNEL_TWO_PASS_MOM, (0, 0, 0)),
+    "two_pass_mom_lds": (scmc.KERNEL_TWO_PASS_MOM, (64, 8, 8)),
+    "fused_mom": (scmc.KERNEL_FUSED_MOM, (64, 8, 16)),
+}
+TAU_GENERAL = ("two_pass", "auto")
 
 
 def _oracle_for(lattice, stencil, shape, psi, g, tau=1.0):
@@ -54,22 +68,39 @@ def _oracle_for(lattice, stencil, shape, psi, g, tau=1.0):
     return O.Oracle(dim, stencil, shape, tau=tau, g=g, psi_self=psi)
 
 
-@pytest.mark.parametrize("kernel", [scmc.KERNEL_TWO_PASS, scmc.KERNEL_AUTO,
-                                    scmc.KERNEL_TWO_PASS_MOM, scmc.KERNEL_FUSED_MOM])
+def _initial_state(case):
+    lattice, _, shape, _, _, init = CASES[case]
+    if init == "random":
+        return _random_state(shape, 100 + case)
+    if lattice == scmc.D2Q9:
+        return inputs.droplet(shape[1], shape[0], R=shape[0] / 4)
+    nz, ny, nx = shape
+    return inputs.droplet(nx, ny, nz, R=min(shape) / 3, bulk=(1.06, -0.001, -0.001, 1.06))
+
+
+@pytest.mark.parametrize("design", list(DESIGNS))
+@pytest.mark.parametrize("tau", [1.0, 0.8])
 @pytest.mark.parametrize("storage,tol,steps", [(scmc.F64, 1e-12, 25), (scmc.F32, 2e-6, 25)])
 @pytest.mark.parametrize("case", range(len(CASES)))
-def test_populations_match_oracle(case, storage, tol, steps, kernel):
-    lattice, stencil, shape, psi, g = CASES[case]
-    print(f"case {case} storage {storage} kernel {kernel} shape {shape}", flush=True)
-    nA, nB = _random_state(shape, 100 + case)
-    tau = 0.8 if case % 2 else 1.0
-    if kernel in (scmc.KERNEL_TWO_PASS_MOM, scmc.KERNEL_FUSED_MOM) and tau != 1.0:
+def test_populations_match_oracle(case, storage, tol, steps, tau, design):
+    """Every design at tau = 1 (the configurations of the benchmark), and the
+    tau-general designs also at tau = 0.8, against the oracle: populations,
+    fields and statistics after 25 steps."""
+    lattice, stencil, shape, psi, g, _ = CASES[case]
+    kernel, tile = DESIGNS[design]
+    if tau != 1.0 and design not in TAU_GENERAL:
         pytest.skip("moment designs need tau = 1")
-    if kernel == scmc.KERNEL_FUSED_MOM and (lattice == scmc.D2Q9 or storage == scmc.F64):
-        pytest.skip("fused designs are D3Q19 with FP32-compute storage")
+    if design in ("fused_mom", "two_pass_mom_lds") and (lattice == scmc.D2Q9 or storage == scmc.F64):
+        pytest.skip("fused and LDS-staged designs are D3Q19 with FP32-compute storage")
+    print(f"case {case} storage {storage} tau {tau} design {design} shape {shape}", flush=True)
+    nA, nB = _initial_state(case)
     p = scmc.problem(lattice, stencil, shape, tau=tau, g=g, psi_self=psi, storage=storage,
-                     kernel=kernel)
+                     kernel=kernel, tile=tile)
     sim = scmc.Sim(p)
+    if kernel != scmc.KERNEL_AUTO:
+        assert sim.scmc_config() == (kernel, tile)
+    elif tau == 1.0:
+        assert sim.scmc_config() == (scmc.KERNEL_TWO_PASS_MOM, (0, 0, 0))
     sim.scmc_set_density(nA, nB)
     sim.scmc_step(steps)
     f, step = sim.scmc_get_populations()
@@ -100,18 +131,24 @@ def test_populations_match_oracle(case, storage, tol, steps, kernel):
     np.testing.assert_allclose(st["mass"], so2["mass"], rtol=1e-13)
     assert np.abs(st["momentum"] - so2["momentum"]).max() < 1e-10
     assert abs(st["max_u"] - so2["max_u"]) < 1e-12
+    np.testing.assert_array_equal(st["min_n"], so2["min_n"])
     sim.close()
 
 
+@pytest.mark.parametrize("design", ["auto", "two_pass_mom_lds"])
 @pytest.mark.parametrize("storage,bits", [(scmc.F16_OFF, 11), (scmc.BF16_OFF, 8)])
-def test_offset_storage_single_step(storage, bits):
+def test_offset_storage_single_step(storage, bits, design):
     """One step from an equilibrium start: the stored h = f* - w n0 carries the
-    rounding of the storage format only."""
+    rounding of the storage format only.  Both forms of the moment two-pass:
+    direct stencil gathers and the LDS-staged collision pass."""
     shape = (10, 12, 66)
     nA, nB = inputs.droplet(66, 12, 10, R=5.0)
     g = ((0.0, 1.8), (1.8, 0.0))
-    p = scmc.problem(scmc.D3Q19, scmc.E6, shape, g=g, storage=storage, n0=(0.52, 0.52))
+    kernel, tile = DESIGNS[design]
+    p = scmc.problem(scmc.D3Q19, scmc.E6, shape, g=g, storage=storage, n0=(0.52, 0.52),
+                     kernel=kernel, tile=tile)
     sim = scmc.Sim(p)
+    assert sim.scmc_config() == (scmc.KERNEL_TWO_PASS_MOM, tile)
     sim.scmc_set_density(nA, nB)
     f0, _ = sim.scmc_get_populations()
     sim.scmc_step(1)
@@ -291,6 +328,54 @@ def test_batch_in_member_chunks_matches_single_runs(graph_steps):
     b.close()
 
 
+G_SYM = ((0.0, 1.8), (1.8, 0.0))
+G_ASYM = ((-0.2, 1.8), (1.8, 0.0))
+
+
+@pytest.mark.parametrize("graph_steps", [0, 4])
+@pytest.mark.parametrize("storage,tol", [(scmc.F64, 1e-12), (scmc.F32, 2e-6)])
+def test_batch_members_match_oracle(storage, tol, graph_steps):
+    """The batched sweep (Sec. 4's sweep over droplet sizes and couplings) in
+    its benchmark design against the oracle, member by member: uneven boxes
+    (one with rows that are not a multiple of 64), symmetric couplings and the
+    asymmetric g_AA = -0.2 with B-rich droplets between the flat-stage guess
+    values, and a 128^3 member whose moment field passes the 48 MB chunk
+    budget, so the tile list runs as three chunks ([0, 1], [2], [3]).  Every
+    population after 25 steps, with direct launches and with graphs of 4
+    steps (six replays and one direct step)."""
+    members = [((20, 20, 20), G_SYM, True, 5.0),
+               ((18, 22, 70), G_ASYM, False, 6.0),
+               ((128, 128, 128), G_SYM, False, 24.0),
+               ((24, 24, 24), G_ASYM, False, 6.0)]
+    ps, inits = [], []
+    for shape, g, a_rich, R0 in members:
+        nz, ny, nx = shape
+        ps.append(scmc.problem(scmc.D3Q19, scmc.E6, shape, g=g, storage=storage))
+        bulk = inputs.FLAT_GUESS[g[0][0]]
+        inits.append(inputs.droplet(nx, ny, nz, R=R0, a_rich=a_rich, bulk=bulk))
+    b = scmc.Batch(ps)
+    for i, (nA, nB) in enumerate(inits):
+        b.scmc_batch_set_density(i, nA, nB)
+    b.scmc_batch_set_graph_steps(graph_steps)
+    b.scmc_batch_step(25)
+    perm = _perm(scmc.D3Q19, 3)
+    for i, ((shape, g, _, R0), (nA, nB)) in enumerate(zip(members, inits)):
+        f, step = b.scmc_batch_get_populations(i)
+        o = O.Oracle(3, 6, shape, g=g)
+        o.set_density(nA, nB)
+        o.run(25)
+        fo = o.f[:, perm]
+        err = np.abs(f - fo).max()
+        print(f"member {i} shape {shape} g_AA {g[0][0]} storage {storage} graph {graph_steps}: "
+              f"max |f - f_oracle| = {err:.3g}", flush=True)
+        assert step == 25 and np.isfinite(f).all()
+        assert err < tol, (i, err)
+        st, so = b.scmc_batch_stats_get(i), o.stats()
+        np.testing.assert_allclose(st["mass"], so["mass"],
+                                   rtol=1e-12 if storage == scmc.F64 else 1e-6)
+    b.close()
+
+
 def test_full_size_sampled_single_step():
     """128^3 D3Q19 / E6 FP32 (the benchmark workload and launch): one step from
     the droplet start; the post-collision populations at sampled sites against
@@ -326,15 +411,20 @@ _GC = -np.e ** 2 / 3.0
 
 @pytest.mark.parametrize("stencil,psi,g", [
     (scmc.E6, scmc.PSI_N, ((0.0, 1.8), (1.8, 0.0))),
+    (scmc.E6, scmc.PSI_N, ((-0.2, 1.8), (1.8, 0.0))),
     (scmc.E4, scmc.PSI_EXP_NEG_INV, ((_GC * 0.6, 0.5), (0.5, _GC * 0.6)))])
 def test_slab_pipelined_moment_pass_single_step(stencil, psi, g):
     """A lattice whose moment field (85 MB) exceeds the slab threshold runs the
     moment two-pass in z-slabs (seven of 13-14 planes), pass 2 of each slab
     after pass 1 of the next.  One step from a droplet against the oracle
     site by site, on every plane (so on both sides of every slab boundary),
-    on the interface and in the bulk."""
+    on the interface and in the bulk.  The asymmetric coupling g_AA = -0.2
+    holds a B-rich droplet, as the 256^3 workload does."""
     nz, ny, nx, R0 = 96, 192, 192, 30.0
-    nA, nB = inputs.droplet(nx, ny, nz, R=R0)
+    if g[0][0] == -0.2:
+        nA, nB = inputs.droplet(nx, ny, nz, R=R0, a_rich=False, bulk=inputs.FLAT_GUESS[-0.2])
+    else:
+        nA, nB = inputs.droplet(nx, ny, nz, R=R0)
     sim = scmc.Sim(scmc.problem(scmc.D3Q19, stencil, (nz, ny, nx), g=g, psi_self=psi,
                                 storage=scmc.F32))
     sim.scmc_set_density(nA, nB)
@@ -358,6 +448,37 @@ def test_slab_pipelined_moment_pass_single_step(stencil, psi, g):
                          for i in range(19)] for J in range(2)])
         worst = max(worst, np.abs(got - want).max())
     assert worst < 1e-6, worst
+
+
+def test_slab_pipelined_asymmetric_droplet_matches_oracle():
+    """The 256^3 workload's arithmetic (D3Q19 / E6, psi = n, g_AA = -0.2,
+    B-rich droplet, FP32) in its slab schedule on a 96 x 192 x 192 box, 200
+    steps (in graphs of 8) against the oracle: every concentration, and
+    Delta P, C_d and the pressure-tensor line.  FP32 rounding over 200
+    steps of a relaxing droplet: 1e-5 in n, 1e-4 relative in the pressures."""
+    nz, ny, nx, R0, steps = 96, 192, 192, 30.0, 200
+    g = ((-0.2, 1.8), (1.8, 0.0))
+    nA, nB = inputs.droplet(nx, ny, nz, R=R0, a_rich=False, bulk=inputs.FLAT_GUESS[-0.2])
+    sim = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (nz, ny, nx), g=g, storage=scmc.F32))
+    sim.scmc_set_graph_steps(8)
+    sim.scmc_set_density(nA, nB)
+    sim.scmc_step(steps)
+    n = sim.scmc_get_fields()
+    ob = sim.scmc_observables(scmc.OBS_DROPLET, R0)
+    sim.close()
+    o = O.Oracle(3, 6, (nz, ny, nx), g=g)
+    o.set_density(nA, nB)
+    o.run(steps)
+    # the line observables of a non-cubic box run along +x from the centre
+    # node (nz/2, ny/2, nx/2) out to nx/2
+    oo = o.droplet_observables(R0)
+    dn = np.abs(n - o.density()).max()
+    print(f"max |dn| {dn:.3g}, dP {ob['dP']:.9g} ({oo['dP']:.9g}), C_d {ob['C_d']:.9g} "
+          f"({oo['C_d']:.9g})", flush=True)
+    assert dn < 1e-5
+    assert abs(ob["dP"] - oo["dP"]) < 1e-4 * abs(oo["dP"])
+    assert abs(ob["C_d"] - oo["C_d"]) < 1e-4 * abs(oo["C_d"])
+    assert np.abs(ob["PT"] - oo["PT"]).max() < 1e-4 * np.abs(oo["PT"]).max()
 
 
 def test_slab_pipelined_moment_pass_graph_and_fused():
@@ -646,7 +767,7 @@ def test_unequal_tau_matches_oracle(case, storage, tol, design):
     damps the non-conserved modes by only |1 - 1/tau_A| = 0.43 per step
     (0.25 at tau = 0.8), so rounding errors of the far-from-equilibrium
     random start persist longer; 4e-6 is about 64 u."""
-    lattice, stencil, shape, psi, g = CASES[case]
+    lattice, stencil, shape, psi, g, _ = CASES[case]
     kernel, tile = {"two_pass": (scmc.KERNEL_TWO_PASS, (0, 0, 0)),
                     "auto": (scmc.KERNEL_AUTO, (0, 0, 0)),
                     "fused": (scmc.KERNEL_FUSED, (64, 4, 16))}[design]
