@@ -190,7 +190,8 @@ int scmc_destroy(scmc_sim *s);
  * next step, the state is the first 2*Q*N values of the storage type at the
  * start of the workspace, laid out [J][i][z][y][x]; value (J, i, x) is the
  * post-collision f*_i^J(x) that the next step streams to x + xi_i (FP16 /
- * BF16: the offset f* - w_i n0_J). */
+ * BF16: the offset f* - w_i n0_J).  scmc_step_static reads and writes
+ * buffers of this layout. */
 int scmc_set_density(scmc_sim *s, const double *nA, const double *nB);
 
 /* Advance nsteps >= 0 time steps, asynchronously.  With graph steps k > 0
@@ -198,6 +199,25 @@ int scmc_set_density(scmc_sim *s, const double *nA, const double *nB);
 int scmc_step(scmc_sim *s, int64_t nsteps);
 int scmc_set_graph_steps(scmc_sim *s, int k);
 int scmc_synchronize(scmc_sim *s);
+
+/* For callers that cannot allocate device memory and hold no workspace (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): one time step of problem p, as scmc_step takes it, from the
+ * caller's device populations src to dst (distinct buffers of 2*Q*N values of
+ * the storage type, in the device layout described at scmc_set_density), on
+ * the current device and the given stream (NULL = default).  The kernel
+ * design is chosen as scmc_create does; the density / moment field of the
+ * two-pass designs lives in a static device array of the library,
+ * SCMC_STATIC_SCRATCH_BYTES on every GPU it runs on, held until the process
+ * ends.  Nothing is allocated.  Every call on one GPU shares that array and
+ * fully rewrites the part it reads, so calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Returns SCMC_ENOSPACE when the lattice needs more than the array (7 values
+ * of the compute precision per site: 2.39M sites FP32/FP16/BF16, 1.19M FP64),
+ * SCMC_EUNSUPPORTED for stochastic rounding (its step counter lives in a
+ * workspace); the text is in scmc_last_error(NULL) of the calling thread. */
+#define SCMC_STATIC_SCRATCH_BYTES (64u << 20)
+int scmc_step_static(const scmc_problem *p, const void *src, void *dst, void *stream);
 
 /* n_J(x, t) and, when u is not NULL, the common velocity u[c*N + s]
  * (c = 0..2) of the current state.  Synchronous. */
@@ -311,6 +331,8 @@ int scmc_batch_autotune(scmc_batch *b, const char *cache_path, int *tile);
 /* Kernel design and tile in use by a handle. */
 int scmc_config(scmc_sim *s, int *kernel, int *tile);
 
+/* Text of the last failure on a handle; with NULL, of the calling thread's
+ * last scmc_step_static failure (or "NULL handle"). */
 const char *scmc_last_error(const scmc_sim *s);
 const char *scmc_batch_last_error(const scmc_batch *b);
 const char *scmc_status_str(int status);

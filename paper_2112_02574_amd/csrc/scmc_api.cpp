@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -948,6 +949,87 @@ int scmc_step(scmc_sim *s, int64_t nsteps) {
         });
 }
 
+// ---- the allocation-free step ----------------------------------------------
+// For callers that cannot allocate: the density / moment field of the
+// two-pass designs lives in this file-scope device array instead of a caller
+// workspace.  Host code never passes its name as an address (in host code the
+// name is a host-side stand-in): static_scratch() fetches the current GPU's
+// own copy with hipGetSymbolAddress, once per device, and every use goes
+// through that pointer.
+static __device__ __align__(256) unsigned char scratch[SCMC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+thread_local char g_static_err[320] = "";
+
+int static_fail(int status, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_static_err, sizeof g_static_err, fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+// Device address of the current device's scratch array.
+int static_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return static_fail(SCMC_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return static_fail(SCMC_EDEVICE, "device index %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return static_fail(SCMC_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s",
+                               dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SCMC_OK;
+}
+
+}  // namespace
+
+int scmc_step_static(const scmc_problem *p, const void *src, void *dst, void *stream) {
+    g_static_err[0] = '\0';
+    if (!p || !src || !dst) return static_fail(SCMC_EINVAL, "NULL problem or population buffer");
+    if (src == dst) return static_fail(SCMC_EINVAL, "src and dst must be distinct buffers");
+    int rc = validate(p, nullptr);
+    if (rc) return static_fail(rc, "invalid problem (%s)", scmc_status_str(rc));
+    if (p->rounding == SCMC_ROUND_STOCHASTIC)
+        return static_fail(SCMC_EUNSUPPORTED,
+                           "stochastic rounding keeps its step counter in a workspace: use scmc_step");
+    const StepKey key = key_of(*p);
+    int kernel = 0, tile[3] = {0, 0, 0};
+    rc = choose_kernel(*p, key, &kernel, tile);
+    if (rc) return static_fail(rc, "no kernel design for this problem");
+    const Member m = member_of(*p);
+    // the field that scmc_workspace_bytes plans for the same problem: 7
+    // values of the compute precision per site
+    const size_t per_site = 7 * real_bytes(p->storage);
+    const size_t need = per_site * (size_t)m.N;
+    if (need > (size_t)SCMC_STATIC_SCRATCH_BYTES)
+        return static_fail(SCMC_ENOSPACE,
+                           "%d sites need %zu bytes of scratch; the static array holds %zu "
+                           "bytes (at most %zu sites with this storage)",
+                           m.N, need, (size_t)SCMC_STATIC_SCRATCH_BYTES,
+                           (size_t)SCMC_STATIC_SCRATCH_BYTES / per_site);
+    void *scr = nullptr;
+    rc = static_scratch(&scr);
+    if (rc) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    const hipError_t e = kernel == SCMC_KERNEL_FUSED
+                             ? launch_fused(key, m, src, dst, tile, st)
+                             : launch_two_pass(key, m, src, dst, scr, st);
+    if (e != hipSuccess) return static_fail(SCMC_EDEVICE, "step launch: %s", hipGetErrorString(e));
+    return SCMC_OK;
+}
+
 int scmc_synchronize(scmc_sim *s) {
     if (!s) return SCMC_EINVAL;
     HIPCHK(s->c, hipStreamSynchronize(s->c.stream));
@@ -1098,7 +1180,8 @@ int scmc_config(scmc_sim *s, int *kernel, int *tile) {
 }
 
 const char *scmc_last_error(const scmc_sim *s) {
-    return s ? s->c.err.c_str() : "NULL handle";
+    if (s) return s->c.err.c_str();
+    return g_static_err[0] ? g_static_err : "NULL handle";
 }
 const char *scmc_batch_last_error(const scmc_batch *b) {
     return b ? b->c.err.c_str() : "NULL handle";

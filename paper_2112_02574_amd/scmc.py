@@ -131,6 +131,8 @@ _SYMBOLS = {
                                ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "scmc_curvature_fit": ([ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "scmc_step_static": ([ctypes.POINTER(Problem), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                         ctypes.c_int),
     "scmc_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
     "scmc_batch_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
     "scmc_status_str": ([ctypes.c_int], ctypes.c_char_p),
@@ -240,6 +242,33 @@ def scmc_flat_equilibrium(p, lx=128, guess=None, max_steps=200000, tol=1e-12,
     if rc:
         raise ScmcError(rc, "scmc_flat_equilibrium")
     return out, steps.value
+
+
+STATIC_SCRATCH_BYTES = 64 << 20   # SCMC_STATIC_SCRATCH_BYTES
+
+
+def state_bytes(p):
+    """Bytes of one device population buffer of problem p (2 Q N values of
+    the storage type)."""
+    q = 9 if p.lattice == D2Q9 else 19
+    return 2 * q * p.nx * p.ny * p.nz * {F64: 8, F32: 4}.get(p.storage, 2)
+
+
+def scmc_step_static(p, src, dst, stream=None):
+    """One allocation-free step of problem p from the device buffer src to dst
+    (torch CUDA tensors of at least state_bytes(p) bytes, device layout)."""
+    import torch
+    need = state_bytes(p)
+    for t in (src, dst):
+        if not t.is_cuda or t.numel() * t.element_size() < need:
+            raise ValueError(f"population buffers must be CUDA tensors of >= {need} bytes")
+    if stream is None:
+        with torch.cuda.device(src.device):
+            stream = torch.cuda.current_stream()
+    rc = lib().scmc_step_static(ctypes.byref(p), ctypes.c_void_p(src.data_ptr()),
+                                ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
+    if rc:
+        raise ScmcError(rc, "scmc_step_static: " + lib().scmc_last_error(None).decode())
 
 
 def scmc_curvature_fit(curvature, sigma):
