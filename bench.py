@@ -9,8 +9,9 @@ before timing).  A timed step is one lattice update of both components
 (stream + concentrations + Shan-Chen force + common velocity + BGK/Guo
 collide); the FP64 statistics, the pressure-tensor / sigma[R] / R_s
 reductions and the convergence criteria (Delta P change, du, droplet centre)
-run at the paper's monitoring cadence (every 2^11 steps, Sec. 4) and at least
-once inside the timed region.
+run at the paper's monitoring cadence: whenever the run's step count reaches a
+multiple of 2^11 (Sec. 4), inside the timed region when that falls there, and
+once after it for the reported observables otherwise.
 
 Prints one JSON line: MLUPS (million lattice-site updates per second, both
 components), the roofline of the step kernel (algorithmic bytes 4 Q s per
@@ -160,23 +161,45 @@ def summarize_profiles(outdir, L=128):
     print(open(TRACE_MD).read())
 
 
-def cpu_baseline(L, R0, steps):
-    """The FP64 oracle on the same workload, a bounded number of steps."""
+def cpu_baseline(L, R0, steps, steps_1t):
+    """The FP64 oracle on the same workload, a bounded number of steps on all
+    the host threads and a smaller number on one thread."""
     from oracle import oracle as O
     from paper_2112_02574_amd import inputs
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    o = O.Oracle(3, 6, (L, L, L), tau=1.0, g=G_SYM, nthreads=threads)
-    # the oracle takes no input from the GPU library, so it starts from the
-    # plain tanh droplet (1.0 / 0.04): the cost of a step does not depend on it
-    o.set_density(*inputs.droplet(L, L, L, R=R0))
-    o.run(1)  # first touch of the work arrays
-    t0 = time.perf_counter()
-    o.run(steps)
-    dt = time.perf_counter() - t0
-    return {"value": round(L ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"FP64 oracle, {steps} steps of a {L}^3 D3Q19/E6 droplet "
-                      f"({L ** 3 * steps:.3g} site updates, {dt:.1f} s)"}
+
+    def rate(nthreads, nsteps):
+        o = O.Oracle(3, 6, (L, L, L), tau=1.0, g=G_SYM, nthreads=nthreads)
+        # the oracle takes no input from the GPU library, so it starts from the
+        # plain tanh droplet (1.0 / 0.04): the cost of a step does not depend on it
+        o.set_density(*inputs.droplet(L, L, L, R=R0))
+        o.run(1)  # first touch of the work arrays
+        t0 = time.perf_counter()
+        o.run(nsteps)
+        return time.perf_counter() - t0
+
+    dt = rate(threads, steps)
+    out = {"value": round(L ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+           "kind": "oracle",
+           "sample": f"FP64 oracle, {steps} steps of a {L}^3 D3Q19/E6 droplet "
+                     f"({L ** 3 * steps:.3g} site updates, {dt:.1f} s)"}
+    if steps_1t > 0:
+        dt1 = rate(1, steps_1t)
+        out["value_1thread"] = round(L ** 3 * steps_1t / dt1 / 1e6, 3)
+        out["sample_1thread"] = f"{steps_1t} steps on 1 thread ({dt1:.1f} s)"
+    out["cpu"] = _cpu_model()
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _timed(step, steps, stream):
@@ -293,24 +316,33 @@ def run(args):
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     step_ms = 0.0
-    obs = stats = None
+    obs = stats = conv = None
+
+    def monitor():
+        # monitoring reductions (FP64): statistics, pressure tensor, sigma[R], R_s
+        # and the convergence criteria of Sec. 4 (Delta P change, du, centre)
+        return (sim.scmc_stats_get(), sim.scmc_observables(scmc.OBS_DROPLET, R0),
+                sim.scmc_convergence_check(R0))
+
     t0 = time.perf_counter()
-    done = 0
+    done, at = 0, args.warmup
     while done < args.steps:
-        chunk = min(OBS_EVERY, args.steps - done)
+        # the reductions run whenever the run's step count reaches a multiple
+        # of 2^11 (Sec. 4's cadence), inside the timed region when it does
+        chunk = min(OBS_EVERY - at % OBS_EVERY, args.steps - done)
         ev0.record(stream)
         sim.scmc_step(chunk)
         ev1.record(stream)
         ev1.synchronize()
         step_ms += ev0.elapsed_time(ev1)
         done += chunk
-        # monitoring reductions (FP64): statistics, pressure tensor, sigma[R], R_s
-        # and the convergence criteria of Sec. 4 (Delta P change, du, centre)
-        stats = sim.scmc_stats_get()
-        obs = sim.scmc_observables(scmc.OBS_DROPLET, R0)
-        conv = sim.scmc_convergence_check(R0)
+        at += chunk
+        if at % OBS_EVERY == 0:
+            stats, obs, conv = monitor()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if obs is None:  # a run shorter than the cadence: observables after timing
+        stats, obs, conv = monitor()
 
     ms_per_step = wall * 1e3 / args.steps
     mlups = N * args.steps / wall / 1e6
@@ -351,7 +383,7 @@ def run(args):
     if args.variant_steps > 0:
         line["variants"] = variants(args, L, R0, bulk, init, dev, stream)
     if args.cpu_steps > 0:
-        line["cpu_baseline"] = cpu_baseline(L, R0, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(L, R0, args.cpu_steps, args.cpu_steps_1t)
     print(json.dumps(line), flush=True)
 
 
@@ -563,8 +595,10 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=300,
                     help="timed steps of each storage variant and of the batched sweep "
                          "(0 to skip)")
-    ap.add_argument("--cpu-steps", type=int, default=20,
-                    help="oracle steps of the CPU baseline (0 to skip)")
+    ap.add_argument("--cpu-steps", type=int, default=200,
+                    help="oracle steps of the CPU baseline on all threads (0 to skip)")
+    ap.add_argument("--cpu-steps-1t", type=int, default=10,
+                    help="oracle steps of the CPU baseline on one thread (0 to skip)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (torch copy_), the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
