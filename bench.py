@@ -215,50 +215,75 @@ def _timed(step, steps, stream):
     return ev0.elapsed_time(ev1) / steps
 
 
-def variants(args, L, R0, bulk, init, dev, stream):
-    """Step rates of the other storage formats on the same droplet, of the
-    same droplet doubled in size (256^3), and of the 48-member batched sweep,
-    each over ``args.variant_steps`` timed steps."""
-    from paper_2112_02574_amd import inputs
-    from paper_2112_02574_amd import scmc
-    N = L ** 3
-    n0 = (0.5 * (bulk[0] + bulk[2]), 0.5 * (bulk[1] + bulk[3]))
-    out = {}
-    for name, storage, size in (("f64", scmc.F64, 8), ("f16_offset", scmc.F16_OFF, 2),
-                                ("bf16_offset", scmc.BF16_OFF, 2)):
-        s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), g=G_SYM, storage=storage,
-                                  n0=n0), device=dev, stream=stream)
-        if storage != scmc.F64:
-            s.scmc_autotune(args.tune_cache)
-        s.scmc_set_density(*init)
-        ms = _timed(s.scmc_step, args.variant_steps, stream)
-        kernel, tile = s.scmc_config()
-        gbs = 4 * 19 * size * N / (ms * 1e-3) / 1e9
-        out[name] = {"MLUPS": round(N / (ms * 1e3), 1), "kernel": KERNEL_NAMES[kernel],
-                     "tile": list(tile), "bytes_per_site": 4 * 19 * size,
-                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-        s.close()
-    # a lattice whose moment field outgrows the caches: the 256^3 droplet
-    # (R0 = 64) in FP32 with the tuned design (the z-slab moment two-pass)
-    Lb = 2 * L
-    s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (Lb, Lb, Lb), g=G_SYM, storage=scmc.F32),
+# bytes per site update (read + write every population once) by storage;
+# node storage keeps the rest populations in FP32: 36 x 2 + 2 x 4 each way
+STORAGE_BYTES = {"f64": 608, "f32": 304, "f16_offset": 152, "bf16_offset": 152,
+                 "f16_node": 160, "bf16_node": 160}
+PRECISION_JSON = os.path.join(ROOT, "profiles", "precision_256cube_asym.json")
+
+
+def _storage_kinds(scmc):
+    return (("f64", scmc.F64), ("f32", scmc.F32), ("f16_offset", scmc.F16_OFF),
+            ("bf16_offset", scmc.BF16_OFF), ("f16_node", scmc.F16_NODE),
+            ("bf16_node", scmc.BF16_NODE))
+
+
+def _storage_rate(args, scmc, shape, g, storage, n0, init, dev, stream, bps):
+    s = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, shape, g=g, storage=storage, n0=n0),
                  device=dev, stream=stream)
-    s.scmc_autotune(args.tune_cache)
-    s.scmc_set_density(*inputs.droplet(Lb, Lb, Lb, R=2 * R0, bulk=bulk))
+    if storage != scmc.F64:
+        s.scmc_autotune(args.tune_cache)
+    s.scmc_set_density(*init)
     ms = _timed(s.scmc_step, args.variant_steps, stream)
     kernel, tile = s.scmc_config()
-    Nb = Lb ** 3
-    out[f"f32_{Lb}cube"] = {"MLUPS": round(Nb / (ms * 1e3), 1), "kernel": KERNEL_NAMES[kernel],
-                            "tile": list(tile), "bytes_per_site": 304,
-                            "hbm_frac": round(304 * Nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     s.close()
+    N = shape[0] * shape[1] * shape[2]
+    return {"MLUPS": round(N / (ms * 1e3), 1), "kernel": KERNEL_NAMES[kernel], "tile": list(tile),
+            "bytes_per_site": bps, "hbm_frac": round(bps * N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def variants(args, L, R0, bulk, init, dev, stream):
+    """Step rates of the other storage formats on the same droplet; of the
+    256^3 asymmetric workload (B-rich droplet, g_AA = -0.2) in every storage,
+    each beside its R_s and sigma_s error against FP64 storage from the
+    precision study (profiles/precision_256cube_asym.json, 61440 steps); and
+    of the 48-member batched sweep, each over ``args.variant_steps`` timed
+    steps."""
+    from paper_2112_02574_amd import inputs
+    from paper_2112_02574_amd import scmc
+    n0 = (0.5 * (bulk[0] + bulk[2]), 0.5 * (bulk[1] + bulk[3]))
+    out = {}
+    for name, storage in _storage_kinds(scmc):
+        if name == "f32":
+            continue
+        out[name] = _storage_rate(args, scmc, (L, L, L), G_SYM, storage, n0, init, dev, stream,
+                                  STORAGE_BYTES[name])
+    # the 256^3 asymmetric droplet: its moment field outgrows the caches, so
+    # the moment two-pass runs in z-slabs
+    bulk_asym, _ = scmc.scmc_flat_equilibrium(
+        scmc.problem(scmc.D3Q19, scmc.E6, (128, 128, 128), g=G_ASYM, storage=scmc.F64),
+        lx=128, guess=inputs.FLAT_GUESS[-0.2], tol=1e-10, device=dev, stream=stream)
+    Lb = 2 * L
+    init_b = inputs.droplet(Lb, Lb, Lb, R=Lb / 4, a_rich=False, bulk=bulk_asym)
+    n0_b = (0.5 * (bulk_asym[0] + bulk_asym[2]), 0.5 * (bulk_asym[1] + bulk_asym[3]))
+    acc = {}
+    if os.path.exists(PRECISION_JSON):
+        with open(PRECISION_JSON) as fh:
+            acc = json.load(fh)
+    c5 = {"workload": f"D3Q19 E6 {Lb}^3 B-rich droplet R0={Lb / 4:g} g_AB=1.8 g_AA=-0.2 psi=n",
+          "accuracy_steps": acc.get("steps")}
+    for name, storage in _storage_kinds(scmc):
+        r = _storage_rate(args, scmc, (Lb, Lb, Lb), G_ASYM, storage, n0_b, init_b, dev, stream,
+                          STORAGE_BYTES[name])
+        a = acc.get("runs", {}).get(name, {})
+        r["abs_err_R_s_vs_f64"] = a.get("abs_err_R_s")
+        r["rel_err_sigma_s_vs_f64"] = a.get("rel_err_sigma_s")
+        c5[name] = r
+    out[f"asym_{Lb}cube"] = c5
     # the batched sweep: 48 droplets on 48^3..160^3 boxes, symmetric and
     # asymmetric couplings, FP32, one persistent launch per step
     members = inputs.batch_members()
-    bulks = {0.0: bulk}
-    bulks[-0.2], _ = scmc.scmc_flat_equilibrium(
-        scmc.problem(scmc.D3Q19, scmc.E6, (128, 128, 128), g=G_ASYM, storage=scmc.F64),
-        lx=128, guess=inputs.FLAT_GUESS[-0.2], tol=1e-10, device=dev, stream=stream)
+    bulks = {0.0: bulk, -0.2: bulk_asym}
     ps = [scmc.problem(scmc.D3Q19, scmc.E6, (m["L"],) * 3, g=m["g"], storage=scmc.F32)
           for m in members]
     b = scmc.Batch(ps, device=dev, stream=stream)
@@ -389,9 +414,10 @@ def run(args):
 
 def precision_study(args, out_md):
     """256^3 D3Q19 / E6 B-rich droplet, R0 = 64, g_AB = 1.8, g_AA = -0.2, psi = n:
-    the same run with populations stored in FP64, FP32, FP16 offsets and BF16
-    offsets (FP32 arithmetic for the last four; offsets rounded to nearest
-    even, or stochastically), observables every 2^11 steps.
+    the same run with populations stored in FP64, FP32, FP16 and BF16 offsets
+    from the global n0 (rounded to nearest even, or stochastically) and FP16
+    and BF16 offsets from the per-node reference (FP32 arithmetic for all but
+    FP64), observables every 2^11 steps.
     FP64 storage stands in for the oracle at this size (its parity with the
     oracle is tested on smaller lattices); errors are stated against it."""
     import torch
@@ -413,7 +439,9 @@ def precision_study(args, out_md):
             ("f16_offset", scmc.F16_OFF, scmc.ROUND_NEAREST),
             ("bf16_offset", scmc.BF16_OFF, scmc.ROUND_NEAREST),
             ("f16_offset_sr", scmc.F16_OFF, scmc.ROUND_STOCHASTIC),
-            ("bf16_offset_sr", scmc.BF16_OFF, scmc.ROUND_STOCHASTIC)):
+            ("bf16_offset_sr", scmc.BF16_OFF, scmc.ROUND_STOCHASTIC),
+            ("f16_node", scmc.F16_NODE, scmc.ROUND_NEAREST),
+            ("bf16_node", scmc.BF16_NODE, scmc.ROUND_NEAREST)):
         sim = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), g=G_ASYM, storage=storage,
                                     n0=n0, rounding=rounding, seed=12345),
                        device=dev, stream=stream)
@@ -476,6 +504,8 @@ def precision_study(args, out_md):
             _fmt(runs[n]["hist"][i]["R_s"], "%.6g") for n in runs) + " |")
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    with open(os.path.splitext(out_md)[0] + ".json", "w") as fh:
+        json.dump(out, fh, indent=1)
     print(json.dumps(out), flush=True)
 
 

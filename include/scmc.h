@@ -69,7 +69,23 @@ typedef enum {
     SCMC_F32 = 1,     /* stored and updated in FP32 */
     SCMC_F16_OFF = 2, /* stored as FP16 h = f - w_i n0_J (round to nearest
                          even), updated in FP32 */
-    SCMC_BF16_OFF = 3 /* same with bfloat16 */
+    SCMC_BF16_OFF = 3, /* same with bfloat16 */
+    SCMC_F16_NODE = 4, /* stored as FP16 2^10 h, h = f* - w_i n_J(x) (round
+                          to nearest even; the exact power-of-two scale keeps
+                          offsets down to 2^-24 out of the FP16 subnormals),
+                          the offset from the equilibrium at
+                          rest of the node x where f* was collided: n_J(x)
+                          is that node's density, kept in FP32 beside the
+                          populations, so the stored offsets carry only the
+                          departure from rest (zero in a bulk at rest) and
+                          the minority phase keeps its precision.  The
+                          rest populations, which do not stream, are kept
+                          in FP32 and close each node's mass balance on the
+                          decoded moving ones.  Updated in FP32.  D3Q19, tau =
+                          1, the moment two-pass (TWO_PASS_MOM or AUTO),
+                          nearest rounding, single lattices only
+                          (SCMC_EUNSUPPORTED otherwise); n0 is unused */
+    SCMC_BF16_NODE = 5 /* the same with bfloat16 */
 } scmc_storage;
 typedef enum {
     SCMC_KERNEL_AUTO = 0,        /* tau_A = tau_B = 1: TWO_PASS_MOM; otherwise
@@ -190,8 +206,10 @@ int scmc_destroy(scmc_sim *s);
  * next step, the state is the first 2*Q*N values of the storage type at the
  * start of the workspace, laid out [J][i][z][y][x]; value (J, i, x) is the
  * post-collision f*_i^J(x) that the next step streams to x + xi_i (FP16 /
- * BF16: the offset f* - w_i n0_J).  scmc_step_static reads and writes
- * buffers of this layout. */
+ * BF16: the offset f* - w_i n0_J; node storage: the offset f* - w_i n_J(x)
+ * for i > 0, with the n_J(x) and the rest populations f*_0 held as FP32
+ * pairs per node in the workspace's moment field).  scmc_step_static reads and writes buffers of
+ * this layout (node storage: SCMC_EUNSUPPORTED). */
 int scmc_set_density(scmc_sim *s, const double *nA, const double *nB);
 
 /* Advance nsteps >= 0 time steps, asynchronously.  With graph steps k > 0

@@ -28,6 +28,7 @@ template <class F> static bool with_ops(const StepKey &k, F &&fn) {
 }
 
 bool fused_supported(const StepKey &k, const int *tile) {
+    if (k.node) return false;  // node storage runs in the moment two-pass only
     return with_ops(k, [&](auto ops) { return decltype(ops)::supported(k, tile); });
 }
 

@@ -179,6 +179,18 @@ struct StoreF16 {
         const T h = __half_as_ushort(__float2half_rn(v - ref));
         __builtin_nontemporal_store(h, p + i);
     }
+    // Node storage (offsets from the node's own rest equilibrium, which are
+    // small where the flow is slow): the offset is scaled by 2^10 before it
+    // is rounded, so offsets down to 2^-24 stay normal numbers with 11
+    // significant bits (and up to 64 in size) instead of falling into the
+    // half subnormals; the power-of-two scale itself is exact.
+    static constexpr float NODE_SCALE = 1024.0f, NODE_UNSCALE = 1.0f / 1024.0f;
+    __device__ __forceinline__ static T to_node(R v, R ref) {
+        return __half_as_ushort(__float2half_rn((v - ref) * NODE_SCALE));
+    }
+    __device__ __forceinline__ static R from_node(T v, R ref) {
+        return __half2float(__ushort_as_half(v)) * NODE_UNSCALE + ref;
+    }
     // Stochastic rounding: 13 random bits added below the half's last
     // mantissa bit, then truncation.  Half subnormals (|h| < 2^-14) are
     // rounded to nearest, their absolute error being below 2^-25.
@@ -224,6 +236,9 @@ struct StoreBF16 {
         const T h = f32_to_bf16_rne(v - ref);
         __builtin_nontemporal_store(h, p + i);
     }
+    // node storage: bfloat16 has the binary32 exponent range, no scale
+    __device__ __forceinline__ static T to_node(R v, R ref) { return to_raw(v, ref); }
+    __device__ __forceinline__ static R from_node(T v, R ref) { return from_raw(v, ref); }
     // Stochastic rounding: 16 random bits added below the kept half of the
     // binary32 pattern, then truncation (sign-magnitude: unbiased for both
     // signs); infinities and NaN go the nearest-even way.

@@ -63,6 +63,23 @@ __device__ __forceinline__ void pull64(const Member &m,
         const int ys = wrap1(y - L::CY[i], m.ny);
         const int zs = D == 3 ? wrap1(z - L::CZ[i], m.nz) : 0;
         const long s = ((long)zs * m.ny + ys) * m.nx + xs;
+        if constexpr (sizeof(typename ST::T) == 2) {
+            if (m.ref) {
+                // node storage: decoded exactly as the step's pull does it,
+                // the rest populations from their FP32 field
+                if (i == 0) {
+                    const float2 r = m.rest[s];
+                    f[0][0] = (double)r.x;
+                    f[1][0] = (double)r.y;
+                    continue;
+                }
+                const float2 q = m.ref[s];
+                const float w = (float)L::W[i];
+                f[0][i] = (double)ST::from_node(base[(long)i * m.N + s], node_ref(w, q.x));
+                f[1][i] = (double)ST::from_node(base[(long)(L::Q + i) * m.N + s], node_ref(w, q.y));
+                continue;
+            }
+        }
         f[0][i] = Decode<ST>::get(base, (long)i * m.N + s, L::W[i], m.n0[0]);
         f[1][i] = Decode<ST>::get(base, (long)(L::Q + i) * m.N + s, L::W[i],
                                   m.n0[1]);

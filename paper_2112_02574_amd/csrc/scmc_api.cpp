@@ -32,6 +32,16 @@ int stencil_radius(int st) { return st == SCMC_E4 ? 1 : 2; }
 size_t storage_bytes(int st) {
     return st == SCMC_F64 ? 8 : st == SCMC_F32 ? 4 : 2;
 }
+bool node_storage(int st) { return st == SCMC_F16_NODE || st == SCMC_BF16_NODE; }
+// kernel storage format of a public one (node storage keeps the 16-bit formats)
+int storage_kind(int st) {
+    return st == SCMC_F16_NODE ? ST_F16 : st == SCMC_BF16_NODE ? ST_BF16 : st;
+}
+// values per site of the density / moment field: (n_A, n_B), the momentum,
+// the packed remainders and a spare; with node storage a second (n_A, n_B)
+// slot (the two pair slots are the reference fields of the two buffers) and
+// the FP32 rest populations
+size_t field_values(int st) { return node_storage(st) ? 10 : 7; }
 size_t real_bytes(int st) { return st == SCMC_F64 ? 8 : 4; }
 
 void velocities(int lattice, int *xi, double *w) {
@@ -108,6 +118,27 @@ float f16_to_f32(uint16_t h) {
 
 // the single-precision offset reference used by the FP16 / BF16 formats
 float offset_ref(double w, double n0) { return (float)w * (float)n0; }
+
+// Node storage on the host, rounded as the kernels round: the reference
+// w_i n_J(x) and the decoded value are single-precision operations of their
+// own (no fused multiply-add).
+float node_ref_host(double w, float n) {
+#pragma clang fp contract(off)
+    const float wf = (float)w;
+    return wf * n;
+}
+// FP16 node offsets are stored scaled by 2^10 (exact), as the kernels do
+uint16_t node_encode(int storage, double v, float ref) {
+#pragma clang fp contract(off)
+    const float h = (float)v - ref;
+    return storage == SCMC_F16_NODE ? f32_to_f16_rne(h * 1024.0f) : f32_to_bf16_rne(h);
+}
+double node_decode(int storage, uint16_t h, float ref) {
+#pragma clang fp contract(off)
+    const float x = storage == SCMC_F16_NODE ? f16_to_f32(h) * (1.0f / 1024.0f) : bf16_to_f32(h);
+    const float d = x + ref;
+    return (double)d;
+}
 
 void encode(int storage, double v, double w, double n0, void *dst, size_t i) {
     switch (storage) {
@@ -231,7 +262,7 @@ int validate(const scmc_problem *p, std::string *why) {
         return bad(SCMC_EINVAL, "unknown stencil");
     if (p->lattice == SCMC_D3Q19 && p->stencil == SCMC_E8)
         return bad(SCMC_EUNSUPPORTED, "E8 stencil is 2D only");
-    if (p->storage < SCMC_F64 || p->storage > SCMC_BF16_OFF)
+    if (p->storage < SCMC_F64 || p->storage > SCMC_BF16_NODE)
         return bad(SCMC_EINVAL, "unknown storage");
     if (p->psi_self != SCMC_PSI_N && p->psi_self != SCMC_PSI_EXP_NEG_INV)
         return bad(SCMC_EINVAL, "unknown psi");
@@ -265,6 +296,19 @@ int validate(const scmc_problem *p, std::string *why) {
         return bad(SCMC_EINVAL, "non-finite n0");
     if (p->rounding != SCMC_ROUND_NEAREST && p->rounding != SCMC_ROUND_STOCHASTIC)
         return bad(SCMC_EINVAL, "unknown rounding");
+    if (node_storage(p->storage)) {
+        if (p->lattice != SCMC_D3Q19)
+            return bad(SCMC_EUNSUPPORTED, "node storage runs on D3Q19");
+        if (!tau_is_one(*p) ||
+            (p->kernel != SCMC_KERNEL_AUTO && p->kernel != SCMC_KERNEL_TWO_PASS_MOM))
+            return bad(SCMC_EUNSUPPORTED,
+                       "node storage runs in the moment two-pass (tau_A = tau_B = 1)");
+        if (p->rounding != SCMC_ROUND_NEAREST)
+            return bad(SCMC_EUNSUPPORTED, "node storage rounds to nearest");
+        if ((double)lattice_q(p->lattice) * p->nx * p->ny * p->nz * storage_bytes(p->storage) >=
+            2147483648.0)
+            return bad(SCMC_EUNSUPPORTED, "node storage needs 32-bit buffer offsets");
+    }
     if (p->rounding == SCMC_ROUND_STOCHASTIC) {
         if (p->storage != SCMC_F16_OFF && p->storage != SCMC_BF16_OFF)
             return bad(SCMC_EINVAL, "stochastic rounding needs FP16 / BF16 offset storage");
@@ -279,7 +323,8 @@ StepKey key_of(const scmc_problem &p) {
     StepKey k;
     k.dim = lattice_dim(p.lattice);
     k.order = p.stencil;
-    k.storage = p.storage;
+    k.storage = storage_kind(p.storage);
+    k.node = node_storage(p.storage) ? 1 : 0;
     k.psi = p.psi_self;
     switch (p.kernel) {
         case SCMC_KERNEL_FUSED_REPULL: k.repull = 1; break;
@@ -296,6 +341,8 @@ StepKey key_of(const scmc_problem &p) {
     if (p.kernel == SCMC_KERNEL_TWO_PASS_MOM && p.tile[0] != 0 && p.lattice == SCMC_D3Q19 &&
         p.storage != SCMC_F64)
         k.mom = 2;
+    // node storage has no fused design: AUTO always means the moment two-pass
+    if (k.node && p.kernel == SCMC_KERNEL_AUTO) k.mom = 1;
     k.big = (double)lattice_q(p.lattice) * p.nx * p.ny * p.nz * storage_bytes(p.storage) >=
             2147483648.0;
     return k;
@@ -321,6 +368,9 @@ Member member_of(const scmc_problem &p) {
     m.sr = p.rounding == SCMC_ROUND_STOCHASTIC;
     m.seed = p.seed;
     m.step_ctr = nullptr;  // bound to the workspace's counter by the handle
+    m.ref = nullptr;       // node storage: set per launch (step_member)
+    m.pair_slot = 0;
+    m.rest = nullptr;
     return m;
 }
 
@@ -330,7 +380,7 @@ int choose_kernel(const scmc_problem &p, const StepKey &k, int *kernel,
     int t[3] = {p.tile[0], p.tile[1], p.tile[2]};
     // at tau = 1 the default is the moment two-pass design (the fastest
     // untuned choice on a 128^3 sweep); the autotuner may pick a fused one
-    if (p.kernel == SCMC_KERNEL_TWO_PASS || p.kernel == SCMC_KERNEL_TWO_PASS_MOM ||
+    if (k.node || p.kernel == SCMC_KERNEL_TWO_PASS || p.kernel == SCMC_KERNEL_TWO_PASS_MOM ||
         (p.kernel == SCMC_KERNEL_AUTO && k.mom && t[0] == 0) ||
         (p.kernel == SCMC_KERNEL_AUTO && p.rounding == SCMC_ROUND_STOCHASTIC)) {
         *kernel = SCMC_KERNEL_TWO_PASS;
@@ -378,7 +428,7 @@ Plan plan_of(const std::vector<scmc_problem> &ps, int ntiles) {
         const size_t N = (size_t)p.nx * p.ny * p.nz;
         pop += align_up(2 * (size_t)lattice_q(p.lattice) * N *
                         storage_bytes(p.storage));
-        dens += align_up(7 * N * real_bytes(p.storage));
+        dens += align_up(field_values(p.storage) * N * real_bytes(p.storage));
         nmax = std::max(nmax, N);
         nxmax = std::max(nxmax, (size_t)p.nx);
         nb = std::max(nb, stats_blocks(member_of(p)));
@@ -429,6 +479,29 @@ void drop_graphs(Common &c) {
         }
 }
 
+// ---- node storage: reference fields --------------------------------------
+// The moment field of a node-storage lattice holds two (n_A, n_B) pair slots,
+// at values 0 and 6N: slot b is the reference field of population buffer b,
+// the densities its offsets are taken from.  Pass 1 of a step from buffer cur
+// decodes against slot cur and writes the new densities into slot 1 - cur,
+// against which pass 2 encodes buffer 1 - cur.
+// The rest populations (f*_0^A, f*_0^B) follow as FP32 pairs at values 8N.
+int pair_slot_of(int buf) { return buf ? 6 : 0; }
+constexpr int kRestSlot = 8;
+float *ref_field(const Common &c, const Lat &L, int buf) {
+    return (float *)c.dens + (size_t)pair_slot_of(buf) * L.m.N;
+}
+float *rest_field(const Common &c, int N) { return (float *)c.dens + (size_t)kRestSlot * N; }
+// the member as a step from buffer cur launches it (single lattice)
+Member step_member(const Common &c, Member m, int cur) {
+    if (c.key.node) {
+        m.ref = (const float2 *)((const float *)c.dens + (size_t)pair_slot_of(cur) * m.N);
+        m.pair_slot = pair_slot_of(1 - cur);
+        m.rest = (float2 *)rest_field(c, m.N);
+    }
+    return m;
+}
+
 // ---- state transfer (single lattice member) ----------------------------
 // the device buffer holds g_i(x) = f_i(x + xi_i): the post-collision values
 // that the next step pulls
@@ -441,6 +514,57 @@ int upload_state(Common &c, const Lat &L, const double *f, void *dst_dev) {
     velocities(p.lattice, xi, w);
     const size_t sb = storage_bytes(p.storage);
     std::vector<unsigned char> host(2 * q * N * sb);
+    if (node_storage(p.storage)) {
+        // the buffer value at node y is f*_i(y) = f_i(y + xi_i); its reference
+        // is the post-collision density of y, sum_i f*_i(y) (BGK conserves
+        // the node's mass, so this is n_J(y) of the step that produced it)
+        std::vector<double> nref(2 * N, 0.0);
+        std::vector<float> ref(2 * N);
+        auto src_of = [&](int i, int z, int y, int x) {
+            const int zs = (z + xi[3 * i + 2] + p.nz) % p.nz;
+            const int ys = (y + xi[3 * i + 1] + p.ny) % p.ny;
+            const int xs = (x + xi[3 * i] + p.nx) % p.nx;
+            return ((size_t)zs * p.ny + ys) * p.nx + xs;
+        };
+        for (int J = 0; J < 2; ++J)
+            for (int i = 0; i < q; ++i)
+                for (int z = 0; z < p.nz; ++z)
+                    for (int y = 0; y < p.ny; ++y)
+                        for (int x = 0; x < p.nx; ++x)
+                            nref[J * N + ((size_t)z * p.ny + y) * p.nx + x] +=
+                                f[((size_t)J * q + i) * N + src_of(i, z, y, x)];
+        for (size_t t = 0; t < 2 * N; ++t) ref[t] = (float)nref[t];
+        uint16_t *h = (uint16_t *)host.data();
+        for (int J = 0; J < 2; ++J)
+            for (int i = 1; i < q; ++i)
+                for (int z = 0; z < p.nz; ++z)
+                    for (int y = 0; y < p.ny; ++y)
+                        for (int x = 0; x < p.nx; ++x) {
+                            const size_t t = ((size_t)z * p.ny + y) * p.nx + x;
+                            const double v = f[((size_t)J * q + i) * N + src_of(i, z, y, x)];
+                            h[((size_t)J * q + i) * N + t] =
+                                node_encode(p.storage, v, node_ref_host(w[i], ref[J * N + t]));
+                        }
+        // reference field of buffer 0, as (n_A, n_B) pairs per node, and the
+        // FP32 rest populations (the i = 0 planes of the buffer are unused)
+        std::vector<float> pairs(2 * N), rest(2 * N);
+        for (size_t t = 0; t < N; ++t) {
+            pairs[2 * t] = ref[t];
+            pairs[2 * t + 1] = ref[N + t];
+            rest[2 * t] = (float)f[t];
+            rest[2 * t + 1] = (float)f[(size_t)q * N + t];
+        }
+        if (dst_dev != c.pop[0])
+            return fail(c, SCMC_EUNSUPPORTED, "node storage uploads into buffer 0 only");
+        HIPCHK(c, hipMemcpyAsync(ref_field(c, L, 0), pairs.data(), pairs.size() * 4,
+                                 hipMemcpyHostToDevice, c.stream));
+        HIPCHK(c, hipMemcpyAsync(rest_field(c, L.m.N), rest.data(), rest.size() * 4,
+                                 hipMemcpyHostToDevice, c.stream));
+        HIPCHK(c, hipMemcpyAsync(dst_dev, host.data(), host.size(), hipMemcpyHostToDevice,
+                                 c.stream));
+        HIPCHK(c, hipStreamSynchronize(c.stream));
+        return SCMC_OK;
+    }
     for (int J = 0; J < 2; ++J)
         for (int i = 0; i < q; ++i) {
             const double *src = f + ((size_t)J * q + i) * N;
@@ -484,7 +608,39 @@ int download_state(Common &c, const Lat &L, const void *src_dev, double *f) {
     std::vector<unsigned char> host(2 * q * N * sb);
     HIPCHK(c, hipMemcpyAsync(host.data(), src_dev, host.size(),
                              hipMemcpyDeviceToHost, c.stream));
+    std::vector<float> pairs, rest;
+    if (node_storage(p.storage)) {
+        pairs.resize(2 * N);
+        rest.resize(2 * N);
+        const int buf = src_dev == c.pop[1] ? 1 : 0;
+        HIPCHK(c, hipMemcpyAsync(pairs.data(), ref_field(c, L, buf), pairs.size() * 4,
+                                 hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(c, hipMemcpyAsync(rest.data(), rest_field(c, L.m.N), rest.size() * 4,
+                                 hipMemcpyDeviceToHost, c.stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c.stream));
+    if (node_storage(p.storage)) {
+        const uint16_t *h = (const uint16_t *)host.data();
+        for (size_t t = 0; t < N; ++t) {
+            f[t] = (double)rest[2 * t];
+            f[(size_t)q * N + t] = (double)rest[2 * t + 1];
+        }
+        for (int J = 0; J < 2; ++J)
+            for (int i = 1; i < q; ++i)
+                for (int z = 0; z < p.nz; ++z)
+                    for (int y = 0; y < p.ny; ++y) {
+                        const int zs = (z - xi[3 * i + 2] + p.nz) % p.nz;
+                        const int ys = (y - xi[3 * i + 1] + p.ny) % p.ny;
+                        for (int x = 0; x < p.nx; ++x) {
+                            const int xs = (x - xi[3 * i] + p.nx) % p.nx;
+                            const size_t t = ((size_t)zs * p.ny + ys) * p.nx + xs;
+                            f[((size_t)J * q + i) * N + ((size_t)z * p.ny + y) * p.nx + x] =
+                                node_decode(p.storage, h[((size_t)J * q + i) * N + t],
+                                            node_ref_host(w[i], pairs[2 * t + J]));
+                        }
+                    }
+        return SCMC_OK;
+    }
     for (int J = 0; J < 2; ++J)
         for (int i = 0; i < q; ++i) {
             double *dst = f + ((size_t)J * q + i) * N;
@@ -528,15 +684,19 @@ int set_density_impl(Common &c, const Lat &L, const double *nA,
 // The observable kernels get the member's own population pointer (already
 // offset) and a per-call FP64 scratch, so their Member view carries no
 // offsets.
-Member obs_member(const Lat &L) {
+Member obs_member(const Common &c, const Lat &L, const void *pop_dev) {
     Member m = L.m;
     m.pop_off = 0;
     m.dens_off = 0;
+    if (c.key.node) {
+        m.ref = (const float2 *)ref_field(c, L, pop_dev == c.pop[1] ? 1 : 0);
+        m.rest = (float2 *)rest_field(c, L.m.N);
+    }
     return m;
 }
 
 int member_obs_prep(Common &c, const Lat &L, const void *pop_dev) {
-    HIPCHK(c, launch_density64(c.key, obs_member(L), pop_dev, c.dens64,
+    HIPCHK(c, launch_density64(c.key, obs_member(c, L, pop_dev), pop_dev, c.dens64,
                                c.stream));
     return SCMC_OK;
 }
@@ -544,7 +704,7 @@ int member_obs_prep(Common &c, const Lat &L, const void *pop_dev) {
 int stats_impl(Common &c, const Lat &L, const void *pop_base, scmc_stats *out,
                int64_t step) {
     if (!out) return fail(c, SCMC_EINVAL, "out is NULL");
-    const Member m = obs_member(L);
+    const Member m = obs_member(c, L, pop_base);
     int rc = member_obs_prep(c, L, pop_base);
     if (rc) return rc;
     HIPCHK(c, launch_stats(c.key, m, pop_base, c.dens64, c.partials,
@@ -568,7 +728,7 @@ int stats_impl(Common &c, const Lat &L, const void *pop_base, scmc_stats *out,
 
 int fields_impl(Common &c, const Lat &L, const void *pop_base, double *nA,
                 double *nB, double *u) {
-    const Member m = obs_member(L);
+    const Member m = obs_member(c, L, pop_base);
     const size_t N = (size_t)m.N;
     int rc = member_obs_prep(c, L, pop_base);
     if (rc) return rc;
@@ -593,7 +753,7 @@ int obs_impl(Common &c, const Lat &L, const void *pop_base, int kind, double R0,
     if (!out) return fail(c, SCMC_EINVAL, "out is NULL");
     if (kind != SCMC_OBS_FLAT && kind != SCMC_OBS_DROPLET)
         return fail(c, SCMC_EINVAL, "unknown observable kind %d", kind);
-    const Member m = obs_member(L);
+    const Member m = obs_member(c, L, pop_base);
     const int d = L.dim;
     std::memset(out, 0, sizeof *out);
     out->step = step;
@@ -659,8 +819,8 @@ int direct_step_sim(scmc_sim *s) {
     void *dst = c.pop[1 - c.cur];
     hipError_t e = c.kernel == SCMC_KERNEL_FUSED
                        ? launch_fused(c.key, s->lat.m, src, dst, c.tile, c.stream)
-                       : launch_two_pass(c.key, s->lat.m, src, dst, c.dens,
-                                         c.stream);
+                       : launch_two_pass(c.key, step_member(c, s->lat.m, c.cur), src,
+                                         dst, c.dens, c.stream);
     if (e != hipSuccess)
         return fail(c, SCMC_EDEVICE, "step launch: %s", hipGetErrorString(e));
     c.cur ^= 1;
@@ -739,7 +899,8 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
                 break;
             }
             // argument values, in kernel-signature order
-            Member mv = m;
+            const Member ms = batch ? m : step_member(c, m, cur);
+            Member mv = ms;
             const Member *dm = d_members;
             const Tile *dt = d_tiles ? d_tiles + chunks[ch] : nullptr;
             int nt = ntiles;
@@ -764,7 +925,7 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
                 for (const SlabOp &o : slabs) {
                     NodeLaunch nl = o.pass == 1 ? dn : sn;
                     nl.grid = dim3(linear_blocks(m, o.nz, (int)nl.block.x));
-                    mv = m;
+                    mv = ms;
                     mv.zoff = o.z0;
                     mv.znum = o.nz;
                     if (!rc) rc = add(nl, o.pass == 1 ? dargs : sargs);
@@ -1004,6 +1165,9 @@ int scmc_step_static(const scmc_problem *p, const void *src, void *dst, void *st
     if (p->rounding == SCMC_ROUND_STOCHASTIC)
         return static_fail(SCMC_EUNSUPPORTED,
                            "stochastic rounding keeps its step counter in a workspace: use scmc_step");
+    if (node_storage(p->storage))
+        return static_fail(SCMC_EUNSUPPORTED,
+                           "node storage keeps its reference field in a workspace: use scmc_step");
     const StepKey key = key_of(*p);
     int kernel = 0, tile[3] = {0, 0, 0};
     rc = choose_kernel(*p, key, &kernel, tile);
@@ -1067,8 +1231,8 @@ int scmc_convergence_check(scmc_sim *s, double R0, double tol_dP, double tol_du,
     Common &c = s->c;
     if (!c.initialized) return fail(c, SCMC_ESTATE, "state not set");
     const Lat &L = s->lat;
-    const Member m = obs_member(L);
     const void *pop = c.pop[c.cur];
+    const Member m = obs_member(c, L, pop);
     scmc_obs o;
     int rc = obs_impl(c, L, pop, SCMC_OBS_DROPLET, R0, &o, nullptr, nullptr, c.step);
     if (rc) return rc;  // obs_impl leaves the FP64 densities in dens64
@@ -1331,6 +1495,10 @@ static int batch_check(const scmc_problem *ps, int count, std::string *why) {
     for (int i = 0; i < count; ++i) {
         int rc = validate(&ps[i], why);
         if (rc) return rc;
+        if (node_storage(ps[i].storage)) {
+            if (why) *why = "node storage runs on single lattices";
+            return SCMC_EUNSUPPORTED;
+        }
         if (ps[i].lattice != ps[0].lattice || ps[i].stencil != ps[0].stencil ||
             ps[i].storage != ps[0].storage || ps[i].tau[0] != ps[0].tau[0] ||
             ps[i].tau[1] != ps[0].tau[1] ||
@@ -1703,7 +1871,9 @@ int scmc_autotune(scmc_sim *s, const char *cache_path, int *tile) {
         for (const Candidate &cand : cands) {
             apply(c, cand);
             double us = 0;
-            rc = time_steps(c, 2, 6, [&] { return direct_step_sim(s); }, &us);
+            // 20 timed steps: the designs closest in speed differ by a few
+            // per cent, and fewer steps picked the slower one
+            rc = time_steps(c, 4, 20, [&] { return direct_step_sim(s); }, &us);
             if (rc) return rc;
             if (us < best_us) {
                 best_us = us;

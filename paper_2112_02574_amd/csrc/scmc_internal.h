@@ -29,6 +29,15 @@ struct Member {
                          // a two-pass step, read by the second (random stream)
     int zoff, znum;      // z-planes [zoff, zoff + znum) of a launch of the
                          // moment two-pass (the whole lattice: 0, nz)
+    // FP16 / BF16 node storage: reference densities (n_A, n_B) per site
+    // [z][y][x] of the buffer being pulled (nullptr for the other formats),
+    // and the slot (in units of N values) of the (n_A, n_B) pairs that the
+    // moment two-pass writes in pass 1 and reads in pass 2 (0 otherwise)
+    const float2 *ref;
+    int pair_slot;
+    // node storage: the rest populations (f*_0^A, f*_0^B) per site in FP32
+    // (they do not stream: pass 1 reads and pass 2 writes the node's own)
+    float2 *rest;
 };
 
 // A unit of work of the batched launches: member index and tile origin.
@@ -51,6 +60,8 @@ struct StepKey {
                      // same with the collision pass's pairs staged in LDS
     int big = 0;     // 1 when a component's Q planes exceed 2^31 bytes: no
                      // 32-bit buffer offsets (fused designs unavailable)
+    int node = 0;    // FP16 / BF16 offsets from the per-node reference
+                     // (moment two-pass, D3Q19 buffer forms only)
 };
 
 // ---- step kernels (step_kernels.hip)

@@ -117,13 +117,21 @@ __device__ __forceinline__ void site_force_fn(const Member &m, int x, int y, int
     double cA[3] = {0, 0, 0}, cB[3] = {0, 0, 0};
     double sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0};
     const bool selfA = m.self_on & 1, selfB = m.self_on & 2;
+    // periodic column, row and plane offsets of x + d, y + d, z + d for
+    // d = -2..2, formed once: a stencil neighbour is then two additions
+    int xo[5], yo[5], zo[5];
+#pragma unroll
+    for (int d = -2; d <= 2; ++d) {
+        xo[d + 2] = wrap1(x + d, m.nx);
+        yo[d + 2] = wrap1(y + d, m.ny) * m.nx;
+        zo[d + 2] = D == 3 ? wrap1(z + d, m.nz) * (m.nx * m.ny) : 0;
+    }
 #pragma unroll
     for (int a = S::NE / 2; a < S::NE; ++a) {
         constexpr auto T = S::T;
         const int ex = T.e[a][0], ey = T.e[a][1], ez = T.e[a][2];
-        const int zp = D == 3 ? wrap1(z + ez, m.nz) : 0, zm = D == 3 ? wrap1(z - ez, m.nz) : 0;
-        const int tp = (zp * m.ny + wrap1(y + ey, m.ny)) * m.nx + wrap1(x + ex, m.nx);
-        const int tm = (zm * m.ny + wrap1(y - ey, m.ny)) * m.nx + wrap1(x - ex, m.nx);
+        const int tp = zo[2 + ez] + yo[2 + ey] + xo[2 + ex];
+        const int tm = zo[2 - ez] + yo[2 - ey] + xo[2 - ex];
         R pAt, pBt, mAt, mBt;  // N < 2^31 (validated)
         fetch(tp, pAt, pBt);
         fetch(tm, mAt, mBt);
@@ -295,11 +303,15 @@ __device__ __forceinline__ void site_moments(const R (&f)[2][Lattice<D>::Q],
 //   E = w [a_J + 9/2 (xi.u) (n_J xi.u + xi.F_J)]
 // and differ in the sign of
 //   O = w [3 n_J xi.u + 3/2 xi.F_J],   f*_xi = E + O, f*_-xi = E - O.
-// Every f*_i^J goes to sink(J, i, value, w_i n0_J).
-template <int D, class R, class Sink>
-__device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[NMOM],
-                                             const R (&FA)[3], const R (&FB)[3],
-                                             Sink &&sink) {
+// Every f*_i^J goes to emit(J, i, value), which stores it and returns the
+// value the next step's pull will see (the stored value as decoded).  The
+// rest population closes the mass balance sum_i f*_i = n_J against those
+// values with the exact n_J: rounded weights (their binary sum is not exactly
+// 1) and re-rounded sums would otherwise bias the mass by the same relative
+// amount every step.
+template <int D, class R, class Emit>
+__device__ __forceinline__ void collide_tau1_emit(const R (&mom)[NMOM], const R (&FA)[3],
+                                                  const R (&FB)[3], Emit &&emit) {
     using L = Lattice<D>;
     const R nA = mom[0], nB = mom[1];
     const R inv = R(1) / (nA + nB);
@@ -307,7 +319,6 @@ __device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[NMO
     const R uy = (mom[3] + R(0.5) * (FA[1] + FB[1])) * inv;
     const R uz = D == 3 ? (mom[4] + R(0.5) * (FA[2] + FB[2])) * inv : R(0);
     const R uu = ux * ux + uy * uy + uz * uz;
-    const R n0[2] = {(R)m.n0[0], (R)m.n0[1]};
     constexpr Opposite<D> OP = Opposite<D>::make();
 #pragma unroll
     for (int J = 0; J < 2; ++J) {
@@ -328,18 +339,61 @@ __device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[NMO
             const R t = nJ * xu;
             const R E = w * (a + R(4.5) * xu * (t + xF));
             const R O = w * (R(3) * t + R(1.5) * xF);
-            const R fp = E + O, fm = E - O;
-            sink(J, i, fp, w * n0[J]);
-            sink(J, ib, fm, w * n0[J]);
+            const R fp = emit(J, i, E + O), fm = emit(J, ib, E - O);
             moving += (double)fp + (double)fm;
         }
-        // the rest population closes the mass balance sum_i f*_i = n_J with
-        // the exact n_J: rounded weights (their binary sum is not exactly 1)
-        // and re-rounded sums would otherwise bias the mass by the same
-        // relative amount every step
         const double nJx = (double)nJ + (double)mom[5 + J];
-        sink(J, 0, (R)(nJx - moving), (R)L::W[0] * n0[J]);
+        emit(J, 0, (R)(nJx - moving));
     }
+}
+
+// The same with every f*_i^J handed to sink(J, i, value, w_i n0_J), the
+// closure taken on the values as formed.
+template <int D, class R, class Sink>
+__device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[NMOM],
+                                             const R (&FA)[3], const R (&FB)[3],
+                                             Sink &&sink) {
+    using L = Lattice<D>;
+    const R n0[2] = {(R)m.n0[0], (R)m.n0[1]};
+    collide_tau1_emit<D, R>(mom, FA, FB, [&](int J, int i, R v) {
+        sink(J, i, v, (R)L::W[i] * n0[J]);
+        return v;
+    });
+}
+
+// ---- per-node-reference offsets (FP16 / BF16 node storage): a population
+// collided at node x is stored as h = f* - w_i n_J(x), with n_J(x) the FP32
+// density of x, which a reference field keeps beside the buffer.  The
+// product and the sum are rounded on their own (no contraction into a fused
+// multiply-add), so that encoding, decoding and the mass closure agree bit
+// for bit wherever they are formed.
+__device__ __forceinline__ float node_ref(float w, float n) {
+#pragma clang fp contract(off)
+    return w * n;
+}
+
+// The collision of a node-storage site: encodes the moving populations
+// against its own densities mom[0], mom[1] and closes the mass balance on
+// their decoded values, so the rest populations, kept in FP32 (restA, restB:
+// they do not stream), absorb the rounding of the 2Q - 2 moving offsets and
+// the node's mass is kept as with FP32 storage.
+template <int D, class ST, class Sink>
+__device__ __forceinline__ void collide_tau1_node(const typename ST::R (&mom)[NMOM],
+                                                  const typename ST::R (&FA)[3],
+                                                  const typename ST::R (&FB)[3], Sink &&sink,
+                                                  float &restA, float &restB) {
+    using L = Lattice<D>;
+    using R = typename ST::R;
+    collide_tau1_emit<D, R>(mom, FA, FB, [&](int J, int i, R v) {
+        if (i == 0) {
+            (J == 0 ? restA : restB) = v;
+            return v;
+        }
+        const R ref = node_ref((R)L::W[i], mom[J]);
+        const typename ST::T h = ST::to_node(v, ref);
+        sink(J, i, h);
+        return ST::from_node(h, ref);
+    });
 }
 
 // Collide and store f* at site s of the member's block of dst.
@@ -427,8 +481,9 @@ __device__ __forceinline__ PopBuf<ST> make_popbuf(const typename ST::T *pop,
 }
 
 // Pull of site (x, y, z) through buffer descriptors (D3Q19); NT as in
-// pull_site.
-template <class ST, bool NT = false>
+// pull_site.  NODE: the buffer holds per-node-reference offsets, decoded
+// against the reference densities m.ref of the source nodes.
+template <class ST, bool NT = false, bool NODE = false>
 __device__ __forceinline__ void pull_site_buf(const Member &m, const PopBuf<ST> &b,
                                               int x, int y, int z,
                                               typename ST::R (&f)[2][19]) {
@@ -449,12 +504,28 @@ __device__ __forceinline__ void pull_site_buf(const Member &m, const PopBuf<ST> 
         const int s = zo[1 - L::CZ[i]] + yo[1 - L::CY[i]] + xo[1 - L::CX[i]];
         const int voff = s * (int)sizeof(T), soff = i * b.plane_bytes;
         const R w = (R)L::W[i];
-        if (NT && L::CX[i] == 0) {
-            f[0][i] = ST::from_raw(RawBuf<T>::load_nt(b.r[0], voff, soff), w * n0A);
-            f[1][i] = ST::from_raw(RawBuf<T>::load_nt(b.r[1], voff, soff), w * n0B);
+        R refA = w * n0A, refB = w * n0B;
+        if constexpr (NODE) {
+            if (i == 0) {  // the rest populations, FP32 at the node itself
+                const float2 r = m.rest[s];
+                f[0][0] = r.x;
+                f[1][0] = r.y;
+                continue;
+            }
+            const float2 q = m.ref[s];
+            refA = node_ref(w, q.x);
+            refB = node_ref(w, q.y);
+        }
+        const T ra = NT && L::CX[i] == 0 ? RawBuf<T>::load_nt(b.r[0], voff, soff)
+                                         : RawBuf<T>::load(b.r[0], voff, soff);
+        const T rb = NT && L::CX[i] == 0 ? RawBuf<T>::load_nt(b.r[1], voff, soff)
+                                         : RawBuf<T>::load(b.r[1], voff, soff);
+        if constexpr (NODE) {
+            f[0][i] = ST::from_node(ra, refA);
+            f[1][i] = ST::from_node(rb, refB);
         } else {
-            f[0][i] = ST::from_raw(RawBuf<T>::load(b.r[0], voff, soff), w * n0A);
-            f[1][i] = ST::from_raw(RawBuf<T>::load(b.r[1], voff, soff), w * n0B);
+            f[0][i] = ST::from_raw(ra, refA);
+            f[1][i] = ST::from_raw(rb, refB);
         }
     }
 }

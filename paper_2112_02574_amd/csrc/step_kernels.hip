@@ -152,7 +152,7 @@ __device__ __forceinline__ void moments_site(const Member &m,
     Pair<R> pr;
     pr.x = mm[0];
     pr.y = mm[1];
-    reinterpret_cast<Pair<R> *>(base)[s] = pr;
+    reinterpret_cast<Pair<R> *>(base + (long)m.pair_slot * m.N)[s] = pr;
 #pragma unroll
     for (int c = 0; c < D; ++c) base[(2 + c) * (long)m.N + s] = mm[2 + c];
     reinterpret_cast<unsigned *>(base + 5 * (long)m.N)[s] = pack_rem<R>(mm);
@@ -165,7 +165,7 @@ __device__ __forceinline__ void collide_mom_site(const Member &m,
                                                  int x, int y, int z) {
     using R = typename ST::R;
     const R *base = mom + m.dens_off;
-    const Pair<R> *pairs = reinterpret_cast<const Pair<R> *>(base);
+    const Pair<R> *pairs = reinterpret_cast<const Pair<R> *>(base + (long)m.pair_slot * m.N);
     const long s = ((long)z * m.ny + y) * m.nx + x;
     const Pair<R> own = pairs[s];
     R mm[NMOM] = {own.x, own.y, 0, 0, 0, 0, 0};
@@ -195,30 +195,33 @@ __device__ __forceinline__ void collide_mom_site(const Member &m,
 
 // D3Q19 forms with 32-bit buffer offsets (each component's Q planes below
 // 2 GiB): plane offsets go in the scalar offset, lanes carry 32-bit offsets.
-template <class ST>
+// The (n_A, n_B) pairs sit at slot m.pair_slot of the moment field (0 but
+// for node storage, whose pass 1 writes the pairs into the reference field
+// of the buffer that pass 2 fills).
+template <class ST, bool NODE = false>
 __device__ __forceinline__ void moments_site_buf(const Member &m, const PopBuf<ST> &sb,
                                                  typename ST::R *__restrict__ mom, int x,
                                                  int y, int z) {
     using R = typename ST::R;
     R f[2][19], mm[NMOM];
-    pull_site_buf<ST, true>(m, sb, x, y, z, f);
+    pull_site_buf<ST, true, NODE>(m, sb, x, y, z, f);
     site_moments<3, R>(f, mm);
     const int s = (z * m.ny + y) * m.nx + x;
     R *base = mom + m.dens_off;
-    reinterpret_cast<Pair<R> *>(base)[s] = Pair<R>{mm[0], mm[1]};
+    reinterpret_cast<Pair<R> *>(base + (long)m.pair_slot * m.N)[s] = Pair<R>{mm[0], mm[1]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) base[(2 + c) * (long)m.N + s] = mm[2 + c];
     reinterpret_cast<unsigned *>(base + 5 * (long)m.N)[s] = pack_rem<R>(mm);
 }
 
-template <int ORDER, class ST, int PSI>
+template <int ORDER, class ST, int PSI, bool NODE = false>
 __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopBuf<ST> &db,
                                                      const typename ST::R *__restrict__ mom,
                                                      int x, int y, int z) {
     using R = typename ST::R;
     using T = typename ST::T;
     const R *base = mom + m.dens_off;
-    const Pair<R> *pairs = reinterpret_cast<const Pair<R> *>(base);
+    const Pair<R> *pairs = reinterpret_cast<const Pair<R> *>(base + (long)m.pair_slot * m.N);
     const int s = (z * m.ny + y) * m.nx + x;
     const Pair<R> own = pairs[s];
     R mm[NMOM] = {own.x, own.y, 0, 0, 0, 0, 0};
@@ -233,6 +236,15 @@ __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopB
                                         b = q.y;
                                     });
     const int voff = s * (int)sizeof(T);
+    if constexpr (NODE) {
+        float2 r;
+        collide_tau1_node<3, ST>(
+            mm, FA, FB,
+            [&](int J, int i, T h) { RawBuf<T>::store_nt(h, db.r[J], voff, i * db.plane_bytes); },
+            r.x, r.y);
+        m.rest[s] = r;
+        return;
+    }
     if (m.sr) {
         SiteRng rng(m.seed, *m.step_ctr, (unsigned)(m.pop_off + s));
         collide_tau1<3, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
@@ -251,7 +263,7 @@ __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopB
 // a ring of 2 ZR + 2 pair planes (tile + halo, 8 B per node, coalesced), so
 // every pair is fetched about once per chunk instead of once per stencil
 // neighbour; the node's momentum and remainders are read directly.
-template <int TX, int TY, int ZC, int ORDER, class ST, int PSI>
+template <int TX, int TY, int ZC, int ORDER, class ST, int PSI, bool NODE = false>
 __global__ void __launch_bounds__(TX *TY)
     k_collide_mom_lds(Member m, const typename ST::T *__restrict__ src,
                       typename ST::T *__restrict__ dst,
@@ -271,7 +283,7 @@ __global__ void __launch_bounds__(TX *TY)
     const bool active = tx < wx && ty < wy;
     const int nhalo = 2 * HR * (wx + 2 * HR) + wy * 2 * HR;
     const R *base = mom + m.dens_off;
-    const float2 *pairs = reinterpret_cast<const float2 *>(base);
+    const float2 *pairs = reinterpret_cast<const float2 *>(base + (long)m.pair_slot * m.N);
     const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
     const int nxy = m.nx * m.ny;
     for (int k = 0; k < len + 2 * ZR; ++k) {
@@ -294,7 +306,16 @@ __global__ void __launch_bounds__(TX *TY)
             for (int c = 0; c < 3; ++c) mm[2 + c] = base[(2 + c) * (long)m.N + s];
             unpack_rem<R>(reinterpret_cast<const unsigned *>(base + 5 * (long)m.N)[s], mm);
             const int voff = s * (int)sizeof(T);
-            if (m.sr) {
+            if constexpr (NODE) {
+                float2 r;
+                collide_tau1_node<3, ST>(
+                    mm, FA, FB,
+                    [&](int J, int i, T h) {
+                        RawBuf<T>::store_nt(h, db.r[J], voff, i * db.plane_bytes);
+                    },
+                    r.x, r.y);
+                m.rest[s] = r;
+            } else if (m.sr) {
                 SiteRng rng(m.seed, *m.step_ctr, (unsigned)(m.pop_off + s));
                 collide_tau1<3, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
                     RawBuf<T>::store_nt(ST::to_raw_sr(v, ref, rng.next()), db.r[J], voff,
@@ -309,24 +330,25 @@ __global__ void __launch_bounds__(TX *TY)
     }
 }
 
-template <class ST, int BLK>
+template <class ST, int BLK, bool NODE = false>
 __global__ void __launch_bounds__(BLK)
     k_moments_buf(Member m, const typename ST::T *__restrict__ src,
                   typename ST::R *__restrict__ mom) {
     advance_step_counter(m, blockIdx.x == 0);
     const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
     int x, y, z;
-    if (linear_site<BLK>(m, x, y, z)) moments_site_buf<ST>(m, sb, mom, x, y, z);
+    if (linear_site<BLK>(m, x, y, z)) moments_site_buf<ST, NODE>(m, sb, mom, x, y, z);
 }
 
-template <int ORDER, class ST, int PSI, int BLK>
+template <int ORDER, class ST, int PSI, int BLK, bool NODE = false>
 __global__ void __launch_bounds__(BLK)
     k_collide_mom_buf(Member m, const typename ST::T *__restrict__ src,
                       typename ST::T *__restrict__ dst,
                       const typename ST::R *__restrict__ mom) {
     const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
     int x, y, z;
-    if (linear_site<BLK>(m, x, y, z)) collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, z);
+    if (linear_site<BLK>(m, x, y, z))
+        collide_mom_site_buf<ORDER, ST, PSI, NODE>(m, db, mom, x, y, z);
 }
 
 template <class ST>
@@ -495,6 +517,10 @@ static bool dispatch_shape(const StepKey &k, F &&fn) {
 template <int D, class ST> constexpr bool buf_form() {
     return D == 3 && !std::is_same<ST, StoreF64>::value;
 }
+// node storage: the buffer forms of the 16-bit formats
+template <int D, class ST> constexpr bool node_form() {
+    return buf_form<D, ST>() && sizeof(typename ST::T) == 2;
+}
 
 // The LDS-staged collision pass (StepKey::mom == 2) marches 64 x 8 columns
 // through z-chunks of 8 planes (measured on 128^3).
@@ -566,39 +592,51 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
             const dim3 g(linear_blocks(m, m.znum, LIN_BLOCK)), b(LIN_BLOCK, 1, 1);
             bool done = false;
             if constexpr (buf_form<D, ST>()) {
-                const std::vector<SlabOp> slabs = slab_schedule(k, m);
-                if (!slabs.empty()) {
-                    const dim3 b(SLAB_BLOCK, 1, 1);
-                    for (const SlabOp &o : slabs) {
-                        Member ms = m;
-                        ms.zoff = o.z0;
-                        ms.znum = o.nz;
-                        const dim3 g(linear_blocks(m, o.nz, SLAB_BLOCK));
-                        if (o.pass == 1)
-                            hipLaunchKernelGGL((k_moments_buf<ST, SLAB_BLOCK>), g, b, 0, st, ms,
-                                               (const T *)src, (R *)dens);
+                auto go = [&](auto Nc) {
+                    constexpr bool NODE = decltype(Nc)::value;
+                    const std::vector<SlabOp> slabs = slab_schedule(k, m);
+                    if (!slabs.empty()) {
+                        const dim3 b(SLAB_BLOCK, 1, 1);
+                        for (const SlabOp &o : slabs) {
+                            Member ms = m;
+                            ms.zoff = o.z0;
+                            ms.znum = o.nz;
+                            const dim3 g(linear_blocks(m, o.nz, SLAB_BLOCK));
+                            if (o.pass == 1)
+                                hipLaunchKernelGGL((k_moments_buf<ST, SLAB_BLOCK, NODE>), g, b, 0,
+                                                   st, ms, (const T *)src, (R *)dens);
+                            else
+                                hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P, SLAB_BLOCK, NODE>),
+                                                   g, b, 0, st, ms, (const T *)src, (T *)dst,
+                                                   (const R *)dens);
+                        }
+                        done = true;
+                    } else if (k.mom && !k.big) {
+                        dim3 gm, bm, gc, bc;
+                        mom_blocks(m, k.mom == 2, &gm, &bm, &gc, &bc);
+                        hipLaunchKernelGGL((k_moments_buf<ST, LIN_BLOCK, NODE>), gm, bm, 0, st, m,
+                                           (const T *)src, (R *)dens);
+                        if (k.mom == 2)
+                            hipLaunchKernelGGL(
+                                (k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P, NODE>), gc, bc, 0,
+                                st, m, (const T *)src, (T *)dst, (const R *)dens);
                         else
-                            hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P, SLAB_BLOCK>), g, b, 0,
-                                               st, ms, (const T *)src, (T *)dst,
+                            hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P, LIN_BLOCK, NODE>), gc,
+                                               bc, 0, st, m, (const T *)src, (T *)dst,
                                                (const R *)dens);
+                        done = true;
                     }
-                    done = true;
-                } else if (k.mom && !k.big) {
-                    dim3 gm, bm, gc, bc;
-                    mom_blocks(m, k.mom == 2, &gm, &bm, &gc, &bc);
-                    hipLaunchKernelGGL((k_moments_buf<ST, LIN_BLOCK>), gm, bm, 0, st, m,
-                                       (const T *)src, (R *)dens);
-                    if (k.mom == 2)
-                        hipLaunchKernelGGL((k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P>),
-                                           gc, bc, 0, st, m, (const T *)src, (T *)dst,
-                                           (const R *)dens);
-                    else
-                        hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P, LIN_BLOCK>), gc, bc, 0, st, m,
-                                           (const T *)src, (T *)dst, (const R *)dens);
-                    done = true;
+                };
+                if (k.node) {
+                    if constexpr (node_form<D, ST>()) go(std::true_type{});
+                } else {
+                    go(std::false_type{});
                 }
             }
             if (done) {
+            } else if (k.node) {  // node storage runs in the buffer forms only
+                err = hipErrorNotSupported;
+                return;
             } else if (k.mom) {
                 hipLaunchKernelGGL((k_moments<D, ST>), g, b, 0, st, m,
                                    (const T *)src, (R *)dens);
@@ -632,20 +670,28 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dn, NodeLaunch *sn,
             dn->block = sn->block = dim3(LIN_BLOCK, 1, 1);
             dn->shmem = sn->shmem = 0;
             if constexpr (buf_form<D, ST>()) {
-                if (k.mom && !k.big) {
-                    dn->func = (void *)&k_moments_buf<ST, LIN_BLOCK>;
+                auto set = [&](auto Nc) {
+                    constexpr bool NODE = decltype(Nc)::value;
+                    dn->func = (void *)&k_moments_buf<ST, LIN_BLOCK, NODE>;
                     sn->func = k.mom == 2
-                                   ? (void *)&k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P>
-                                   : (void *)&k_collide_mom_buf<O, ST, P, LIN_BLOCK>;
+                                   ? (void *)&k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P, NODE>
+                                   : (void *)&k_collide_mom_buf<O, ST, P, LIN_BLOCK, NODE>;
                     mom_blocks(m, k.mom == 2, &dn->grid, &dn->block, &sn->grid, &sn->block);
                     if (!slab_schedule(k, m).empty()) {  // slab launches: grid set per slab
-                        dn->func = (void *)&k_moments_buf<ST, SLAB_BLOCK>;
-                        sn->func = (void *)&k_collide_mom_buf<O, ST, P, SLAB_BLOCK>;
+                        dn->func = (void *)&k_moments_buf<ST, SLAB_BLOCK, NODE>;
+                        sn->func = (void *)&k_collide_mom_buf<O, ST, P, SLAB_BLOCK, NODE>;
                         dn->block = sn->block = dim3(SLAB_BLOCK, 1, 1);
+                    }
+                };
+                if (k.mom && !k.big) {
+                    if (!k.node) {
+                        set(std::false_type{});
+                    } else if constexpr (node_form<D, ST>()) {
+                        set(std::true_type{});
                     }
                 }
             }
-            ok = true;
+            ok = !k.node || (node_form<D, ST>() && k.mom && !k.big);
         });
     });
     return ok;

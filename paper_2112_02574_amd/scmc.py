@@ -19,12 +19,13 @@ LIBPATH = os.path.join(HERE, "libscmc.so")
 D2Q9, D3Q19 = 0, 1
 E4, E6, E8 = 4, 6, 8
 PSI_N, PSI_EXP_NEG_INV = 0, 1
-F64, F32, F16_OFF, BF16_OFF = 0, 1, 2, 3
+F64, F32, F16_OFF, BF16_OFF, F16_NODE, BF16_NODE = 0, 1, 2, 3, 4, 5
 KERNEL_AUTO, KERNEL_TWO_PASS, KERNEL_FUSED, KERNEL_FUSED_REPULL, KERNEL_FUSED_PIPE = 0, 1, 2, 3, 4
 KERNEL_FUSED_MOM, KERNEL_FUSED_MOM_PIPE, KERNEL_TWO_PASS_MOM = 5, 6, 7
 ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
 OBS_FLAT, OBS_DROPLET = 0, 1
-STORAGE_NAMES = {F64: "f64", F32: "f32", F16_OFF: "f16", BF16_OFF: "bf16"}
+STORAGE_NAMES = {F64: "f64", F32: "f32", F16_OFF: "f16", BF16_OFF: "bf16", F16_NODE: "f16_node",
+                 BF16_NODE: "bf16_node"}
 
 STATUS = {0: "SCMC_OK", -1: "SCMC_EINVAL", -2: "SCMC_EUNSUPPORTED",
           -3: "SCMC_ENOSPACE", -4: "SCMC_EDEVICE", -5: "SCMC_ENONFINITE",
@@ -145,6 +146,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIBPATH):
             raise RuntimeError(f"{LIBPATH} is missing: run __graft_entry__.build() first")
+        # torch first: its HIP runtime must be the one libscmc binds to, or the
+        # process holds two runtimes and neither sees the other's device memory
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIBPATH)
         for name, (args, res) in _SYMBOLS.items():
             fn = getattr(L, name)

@@ -129,3 +129,34 @@ def test_unequal_tau_is_accepted_by_the_tau_general_designs():
         out = ctypes.c_size_t()
         assert scmc.lib().scmc_workspace_bytes(ctypes.byref(p), ctypes.byref(out)) == 0
         assert out.value > 0
+
+
+def test_node_storage_validation():
+    """FP16 / BF16 offsets from the per-node reference: the moment two-pass on
+    single D3Q19 lattices at tau = 1 with nearest rounding, nothing else."""
+    out = ctypes.c_size_t()
+    for st in (scmc.F16_NODE, scmc.BF16_NODE):
+        for kernel in (scmc.KERNEL_AUTO, scmc.KERNEL_TWO_PASS_MOM):
+            p = scmc.problem(scmc.D3Q19, scmc.E6, (16, 16, 16), storage=st, kernel=kernel)
+            assert scmc.lib().scmc_workspace_bytes(ctypes.byref(p), ctypes.byref(out)) == 0
+        # a second (n_A, n_B) slot and the FP32 rest populations: 10 FP32
+        # values per site in the moment field instead of 7
+        n_node = out.value
+        p = scmc.problem(scmc.D3Q19, scmc.E6, (16, 16, 16), storage=scmc.F16_OFF)
+        assert scmc.lib().scmc_workspace_bytes(ctypes.byref(p), ctypes.byref(out)) == 0
+        assert n_node == out.value + 3 * 16 ** 3 * 4
+        bad = [
+            scmc.problem(scmc.D2Q9, scmc.E8, (32, 32), storage=st),
+            scmc.problem(scmc.D3Q19, scmc.E6, (16, 16, 16), storage=st, tau=0.8),
+            scmc.problem(scmc.D3Q19, scmc.E6, (16, 16, 16), storage=st, kernel=scmc.KERNEL_FUSED),
+            scmc.problem(scmc.D3Q19, scmc.E6, (16, 16, 16), storage=st, kernel=scmc.KERNEL_TWO_PASS),
+            scmc.problem(scmc.D3Q19, scmc.E6, (16, 16, 16), storage=st,
+                         rounding=scmc.ROUND_STOCHASTIC),
+        ]
+        for q in bad:
+            assert scmc.lib().scmc_workspace_bytes(ctypes.byref(q), ctypes.byref(out)) == -2
+        q = scmc.problem(scmc.D3Q19, scmc.E6, (16, 16, 16), storage=st)
+        arr = (scmc.Problem * 2)(q, q)
+        assert scmc.lib().scmc_batch_workspace_bytes(arr, 2, ctypes.byref(out)) == -2
+        fake_src, fake_dst = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21)  # never dereferenced
+        assert scmc.lib().scmc_step_static(ctypes.byref(q), fake_src, fake_dst, None) == -2
