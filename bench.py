@@ -44,18 +44,34 @@ KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 OBS_EVERY = 2048
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "step_e6_f32_128cube_traffic.txt")
 TRACE_MD = os.path.join(ROOT, "profiles", "step_e6_f32_128cube_kernel_trace.md")
-PROFILE_COMMANDS = {
-    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace "
-             "-o trace -- python3 bench.py --steps 300 --warmup 20 --cpu-steps 0 --variant-steps 0 --init tanh --kernel two_pass_mom",
-    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch "
-             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh --kernel two_pass_mom",
-    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write "
-             "-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh --kernel two_pass_mom",
-    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_copy_fetch "
-                  "-o cfetch -- python3 bench.py --copy-calib 1024",
-    "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_copy_write "
-                  "-o cwrite -- python3 bench.py --copy-calib 1024",
-}
+# the profiled workloads: the 128^3 droplet in each storage (the benchmark's
+# FP32 one without a suffix) and the 48-member batched sweep
+PROFILE_RUNS = {"f32": "--storage f32 --kernel two_pass_mom",
+                "f16_offset": "--storage f16_offset", "bf16_offset": "--storage bf16_offset",
+                "f16_node": "--storage f16_node", "bf16_node": "--storage bf16_node",
+                "batch48": "--batch-only"}
+
+
+def profile_commands(tag):
+    """The rocprofv3 commands whose output summarize_profiles reads for one
+    profiled workload (repository root, one MI355X)."""
+    sub = "" if tag == "f32" else "_" + tag
+    run = PROFILE_RUNS[tag]
+    return {
+        "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof{sub}_trace "
+                 f"-o trace -- python3 bench.py --steps 300 --warmup 20 --cpu-steps 0 --variant-steps 0 --init tanh {run}",
+        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof{sub}_fetch -o fetch "
+                 f"-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh {run}",
+        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof{sub}_write -o write "
+                 f"-- python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh {run}",
+        "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_copy_fetch "
+                      "-o cfetch -- python3 bench.py --copy-calib 1024",
+        "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_copy_write "
+                      "-o cwrite -- python3 bench.py --copy-calib 1024",
+    }
+
+
+PROFILE_COMMANDS = profile_commands("f32")
 KERNEL_SOURCES = ["paper_2112_02574_amd/csrc/step_kernels.hip",
                   "paper_2112_02574_amd/csrc/fused_impl.h",
                   "paper_2112_02574_amd/csrc/fused_inst.hip",
@@ -91,15 +107,30 @@ def _finite(v):
     return v if isinstance(v, (int, float)) and v == v and abs(v) != float("inf") else None
 
 
-STEP_KERNEL = re.compile(r"scmc::kb?_(fused|density|collide|moments|collide_mom)(_buf)?<")
+STEP_KERNEL = re.compile(r"scmc::kb?_(fused|density|collide|moments|collide_mom)(_buf|_lds)?<")
 
 
-def summarize_profiles(outdir, L=128):
+def summarize_profiles(outdir, tag="f32", L=128):
     """Write the profiles/ summaries from the rocprofv3 CSV output of the
-    commands in PROFILE_COMMANDS (run from the repository root).  A step is
-    one launch of each step kernel (one for the fused designs, two for the
-    two-pass ones); durations and counters are summed over them."""
+    commands of profile_commands(tag) (run from the repository root).  A step
+    is one launch of each step kernel (one for the fused designs, two for the
+    two-pass ones, two per member chunk for the batch); durations and
+    counters are summed over them."""
     import csv
+    from paper_2112_02574_amd import inputs
+    sub = "" if tag == "f32" else "_" + tag
+    cmds = profile_commands(tag)
+    if tag == "batch48":
+        N = sum(m["L"] ** 3 for m in inputs.batch_members())
+        bps, title = 304, "48-member batched sweep (48^3..160^3 droplets), FP32 populations"
+    else:
+        N = L ** 3
+        bps = STORAGE_BYTES[tag]
+        title = f"D3Q19 E6 droplet {L}^3, {tag} populations"
+    traffic_json = TRAFFIC_JSON if tag == "f32" else os.path.join(
+        ROOT, "profiles", f"step_e6_{tag}_traffic.txt")
+    trace_md = TRACE_MD if tag == "f32" else os.path.join(
+        ROOT, "profiles", f"step_e6_{tag}_kernel_trace.md")
 
     def rows(sub, suffix):
         d = os.path.join(outdir, sub)
@@ -111,38 +142,66 @@ def summarize_profiles(outdir, L=128):
              if r["Kernel_Name"].startswith(prefix)]
         return sum(v) / len(v), len(v)
 
-    stats = rows("prof_trace", "_kernel_stats.csv")
+    stats = rows(f"prof{sub}_trace", "_kernel_stats.csv")
+    # the batch's own kernels (its process also runs the FP64 flat stages)
     step_rows = [r for r in stats if STEP_KERNEL.search(r["Name"])
-                 and "density64" not in r["Name"]]
+                 and "density64" not in r["Name"]
+                 and (tag != "batch48" or r["Name"].startswith("void scmc::kb_"))]
     names = [r["Name"].split("(")[0] for r in step_rows]
-    step_us = sum(float(r["AverageNs"]) for r in step_rows) / 1e3
+    # launches per step: one per kernel, or one per member chunk in a batch
+    # (300 + 20 steps in the trace run)
+    step_us = sum(float(r["AverageNs"]) * (float(r["Calls"]) / 320 if tag == "batch48" else 1)
+                  for r in step_rows) / 1e3
     fetch = write = 0.0
     nf = nw = 0
-    for nm in names:
-        f, a = mean_counter("prof_fetch", nm)
-        w, b = mean_counter("prof_write", nm)
-        fetch, write, nf, nw = fetch + f, write + w, nf + a, nw + b
+    have_counters = os.path.isdir(os.path.join(outdir, f"prof{sub}_fetch")) and any(
+        f.endswith("_counter_collection.csv")
+        for f in os.listdir(os.path.join(outdir, f"prof{sub}_fetch")))
+    for nm in (names if have_counters else []):
+        f, a = mean_counter(f"prof{sub}_fetch", nm)
+        w, b = mean_counter(f"prof{sub}_write", nm)
+        # a batch step launches each kernel once per member chunk (the counter
+        # runs of the batch take 20 warm-up and 20 timed steps)
+        per = max(1, round(a / 40)) if tag == "batch48" else 1
+        fetch, write, nf, nw = fetch + f * per, write + w * per, nf + a, nw + b
     cf, _ = mean_counter("prof_copy_fetch", "__amd_rocclr_copyBuffer")
     cw, _ = mean_counter("prof_copy_write", "__amd_rocclr_copyBuffer")
     copy_bytes = 1024 * (1 << 20)
     sf, sw = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
-    N = L ** 3
     hbm = fetch * 1024 * sf + write * 1024 * sw
+    if not have_counters:
+        lines = ["# Kernel trace: " + title, "",
+                 "Command (repository root, one MI355X):", "", "    " + cmds["trace"], "",
+                 "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+        for r in stats[:8]:
+            lines.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f |" % (
+                r["Name"].split("(")[0], r["Calls"], float(r["AverageNs"]) / 1e3,
+                float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+        lines += ["", "Step kernels: %s." % ", ".join("`%s`" % n for n in names), "",
+                  "One step (each kernel's launches per step times its mean duration): %.1f us = "
+                  "%.0f MLUPS; algorithmic %d B/site -> %.0f GB/s (%.1f%% of 8 TB/s)." % (
+                      step_us, N / step_us, bps, bps * N / step_us / 1e3, bps * N / step_us / 1e3 / 80),
+                  "", "No HBM traffic counters: rocprofv3 --pmc runs of this program ended with a "
+                  "segmentation fault of the profiled process before the first step.", ""]
+        with open(trace_md, "w") as fh:
+            fh.write("\n".join(lines))
+        print(open(trace_md).read())
+        return
     traffic = {"kernels": names, "sites": N, "dispatches": {"fetch": nf, "write": nw},
                "fetch_size_kib_per_step": round(fetch, 1),
                "write_size_kib_per_step": round(write, 1),
                "copy_calibration": {"bytes": copy_bytes, "fetch_size_kib": round(cf, 1),
                                     "write_size_kib": round(cw, 1), "fetch_scale": round(sf, 4),
                                     "write_scale": round(sw, 4)},
-               "hbm_bytes_per_launch": round(hbm), "algorithmic_bytes_per_launch": 304 * N,
-               "ratio_to_algorithmic": round(hbm / (304 * N), 4),
+               "hbm_bytes_per_launch": round(hbm), "algorithmic_bytes_per_launch": bps * N,
+               "ratio_to_algorithmic": round(hbm / (bps * N), 4),
                "kernel_source_hash": kernel_source_hash(),
-               "commands": [PROFILE_COMMANDS[k] for k in ("fetch", "write", "copy_fetch", "copy_write")]}
-    with open(TRAFFIC_JSON, "w") as fh:
+               "commands": [cmds[k] for k in ("fetch", "write", "copy_fetch", "copy_write")]}
+    with open(traffic_json, "w") as fh:
         json.dump(traffic, fh, indent=1)
         fh.write("\n")
-    lines = ["# Kernel trace: D3Q19 E6 droplet 128^3, FP32 populations", "",
-             "Command (repository root, one MI355X):", "", "    " + PROFILE_COMMANDS["trace"], "",
+    lines = ["# Kernel trace: " + title, "",
+             "Command (repository root, one MI355X):", "", "    " + cmds["trace"], "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in stats[:8]:
         lines.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f |" % (
@@ -150,15 +209,18 @@ def summarize_profiles(outdir, L=128):
             float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     lines += ["", "Step kernels: %s." % ", ".join("`%s`" % n for n in names),
               "", "One step: %.1f us = %.0f MLUPS; algorithmic %d B/site -> %.0f GB/s "
-              "(%.1f%% of 8 TB/s)." % (step_us, N / step_us, 304, 304 * N / step_us / 1e3,
-                                       304 * N / step_us / 1e3 / 80),
+              "(%.1f%% of 8 TB/s)." % (step_us, N / step_us, bps, bps * N / step_us / 1e3,
+                                       bps * N / step_us / 1e3 / 80),
               "", "HBM traffic per step (rocprofv3 counters summed over the step kernels, scaled by a "
               "1 GiB copy): FETCH_SIZE %.0f KiB x %.3f + WRITE_SIZE %.0f KiB x %.3f = %.1f MB, "
               "%.3f x the algorithmic %.1f MB." % (
-                  fetch, sf, write, sw, hbm / 1e6, hbm / (304 * N), 304 * N / 1e6), ""]
-    with open(TRACE_MD, "w") as fh:
+                  fetch, sf, write, sw, hbm / 1e6, hbm / (bps * N), bps * N / 1e6), ""]
+    if tag == "batch48":
+        lines[-1:-1] = ["The step time is the sum of one launch of each step kernel; the batch launches "
+                        "them once per member chunk, so the trace's averages are per chunk.", ""]
+    with open(trace_md, "w") as fh:
         fh.write("\n".join(lines))
-    print(open(TRACE_MD).read())
+    print(open(trace_md).read())
 
 
 def cpu_baseline(L, R0, steps, steps_1t):
@@ -280,8 +342,18 @@ def variants(args, L, R0, bulk, init, dev, stream):
         r["rel_err_sigma_s_vs_f64"] = a.get("rel_err_sigma_s")
         c5[name] = r
     out[f"asym_{Lb}cube"] = c5
-    # the batched sweep: 48 droplets on 48^3..160^3 boxes, symmetric and
-    # asymmetric couplings, FP32, one persistent launch per step
+    out["batch48_f32"] = _batch_rate(args, bulk, bulk_asym, dev, stream, args.variant_steps)
+    out["steps_each"] = args.variant_steps
+    return out
+
+
+def _batch_rate(args, bulk, bulk_asym, dev, stream, steps, graph=64):
+    """The batched sweep: 48 droplets on 48^3..160^3 boxes, symmetric and
+    asymmetric couplings, FP32, one persistent launch per step, graphs of
+    ``graph`` steps (0: direct launches); step rate over ``steps`` timed
+    steps."""
+    from paper_2112_02574_amd import inputs
+    from paper_2112_02574_amd import scmc
     members = inputs.batch_members()
     bulks = {0.0: bulk, -0.2: bulk_asym}
     ps = [scmc.problem(scmc.D3Q19, scmc.E6, (m["L"],) * 3, g=m["g"], storage=scmc.F32)
@@ -292,17 +364,34 @@ def variants(args, L, R0, bulk, init, dev, stream):
         Lm = m["L"]
         b.scmc_batch_set_density(i, *inputs.droplet(Lm, Lm, Lm, R=m["R0"], a_rich=m["a_rich"],
                                                     bulk=bulks[m["g"][0][0]]))
-    b.scmc_batch_set_graph_steps(64)
-    ms = _timed(b.scmc_batch_step, args.variant_steps, stream)
+    b.scmc_batch_set_graph_steps(graph)
+    ms = _timed(b.scmc_batch_step, steps, stream)
     sites = sum(m["L"] ** 3 for m in members)
     gbs = 4 * 19 * 4 * sites / (ms * 1e-3) / 1e9
-    out["batch48_f32"] = {"MLUPS": round(sites / (ms * 1e3), 1), "sites": sites,
-                          "members": len(members), "tile": list(tile),
-                          "grid": b.scmc_batch_config()[1], "graph_steps": 64,
-                          "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    r = {"MLUPS": round(sites / (ms * 1e3), 1), "sites": sites, "members": len(members),
+         "tile": list(tile), "grid": b.scmc_batch_config()[1], "graph_steps": graph,
+         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     b.close()
-    out["steps_each"] = args.variant_steps
-    return out
+    return r
+
+
+def batch_only(args):
+    """Profiling mode: the batched sweep alone, 20 untimed and --steps timed
+    steps, in direct launches unless --graph is given (rocprofv3's counter
+    collection has crashed the process on graph-launched dispatches)."""
+    import torch
+    from paper_2112_02574_amd import inputs
+    from paper_2112_02574_amd import scmc
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    bulk, _ = scmc.scmc_flat_equilibrium(
+        scmc.problem(scmc.D3Q19, scmc.E6, (128, 128, 128), g=G_SYM, storage=scmc.F64),
+        lx=128, guess=inputs.FLAT_GUESS[0.0], tol=1e-10, device=dev, stream=stream)
+    bulk_asym, _ = scmc.scmc_flat_equilibrium(
+        scmc.problem(scmc.D3Q19, scmc.E6, (128, 128, 128), g=G_ASYM, storage=scmc.F64),
+        lx=128, guess=inputs.FLAT_GUESS[-0.2], tol=1e-10, device=dev, stream=stream)
+    print(json.dumps({"batch48_f32": _batch_rate(args, bulk, bulk_asym, dev, stream, args.steps,
+                                                 graph=args.graph)}), flush=True)
 
 
 def run(args):
@@ -323,8 +412,10 @@ def run(args):
     else:
         bulk, flat_steps = list(inputs.FLAT_GUESS[0.0]), 0
     init = inputs.droplet(L, L, L, R=R0, bulk=bulk)
+    storage = dict(_storage_kinds(scmc))[args.storage]
+    n0 = (0.5 * (bulk[0] + bulk[2]), 0.5 * (bulk[1] + bulk[3]))
     p = scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), tau=1.0, g=G_SYM,
-                     storage=scmc.F32, kernel=KERNELS[args.kernel],
+                     storage=storage, n0=n0, kernel=KERNELS[args.kernel],
                      tile=tuple(args.tile) if args.tile else (0, 0, 0))
     sim = scmc.Sim(p, device=dev, stream=stream)
     if args.tile is None and args.kernel == "auto":
@@ -372,9 +463,15 @@ def run(args):
     ms_per_step = wall * 1e3 / args.steps
     mlups = N * args.steps / wall / 1e6
     kernel_ms = step_ms / args.steps
-    bytes_alg = 4 * 19 * 4 * N  # read + write of 2 x 19 FP32 populations
+    bps = STORAGE_BYTES[args.storage]
+    bytes_alg = bps * N  # read + write of every population once (FP32: 2 x 19 x 4 B each way)
     achieved = bytes_alg / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(N)
+    traffic = measured_traffic(N) if args.storage == "f32" else None
+    # the streaming half of the step without arithmetic, in the same buffers:
+    # the bandwidth ceiling of any design that moves each population once
+    # (it overwrites the state, so it runs after the observables)
+    copy_bytes = 4 * 19 * {"f64": 8, "f32": 4}.get(args.storage, 2) * N
+    copy_gbs = copy_bytes / (sim.scmc_pull_copy(200) * 1e-6) / 1e9
     line = {
         "metric": "MLUPS (2-component D3Q19 Shan-Chen step)",
         "value": round(mlups, 1),
@@ -386,16 +483,21 @@ def run(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"f64": "f64"}.get(args.storage, "f32"),
         "data": "synthetic (tanh droplet between flat-interface bulk values, no dataset)",
-        "config": {"workload": f"D3Q19 E6 droplet {L}^3 R0={R0:g} tau=1 g_AB=1.8 psi=n FP32 SoA",
+        "config": {"workload": f"D3Q19 E6 droplet {L}^3 R0={R0:g} tau=1 g_AB=1.8 psi=n "
+                               f"{args.storage.upper() if args.storage == 'f32' else args.storage} SoA",
+                   "storage": args.storage,
                    "sites": N, "kernel": KERNEL_NAMES[kernel],
                    "tile": list(tile), "graph_steps": args.graph,
                    "reductions_every": OBS_EVERY, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel_ms": round(kernel_ms, 5),
-                     "bytes_per_site": 4 * 19 * 4},
+                     "bytes_per_site": bps,
+                     "pull_copy_GBs": round(copy_gbs, 1),
+                     "pull_copy_frac": round(copy_gbs / HBM_PEAK_GBS, 4),
+                     "achieved_over_pull_copy": round(achieved / copy_gbs, 4)},
         "observables": {"dP": _finite(obs["dP"]), "R_s": _finite(obs["R_s"]),
                         "sigma_s": _finite(obs["sigma_s"]), "step": obs["step"],
                         "mass": stats["mass"].tolist(), "max_u": _finite(stats["max_u"]),
@@ -495,8 +597,7 @@ def precision_study(args, out_md):
             name, r["kernel"], r["MLUPS"], _fmt(f["dP"], "%.8g"), _fmt(f["R_s"], "%.8g"),
             _fmt(f["sigma_s"], "%.8g"), _fmt(eR, "%.3g"), _fmt(es, "%.3g"), en))
         out["runs"][name] = {"MLUPS": r["MLUPS"], "kernel": r["kernel"], "final": f,
-                             "abs_err_R_s": eR, "rel_err_sigma_s": es, "max_abs_err_n_axis": en,
-                             "history": r["hist"]}
+                             "abs_err_R_s": eR, "rel_err_sigma_s": es, "max_abs_err_n_axis": en}
     lines += ["", "History of R_s (every 2^11 steps):", "",
               "| step | " + " | ".join(runs) + " |", "|---|" + "---|" * len(runs)]
     for i, h in enumerate(ref["hist"]):
@@ -645,15 +746,25 @@ def main():
     ap.add_argument("--tolman-max-steps", type=int, default=400000)
     ap.add_argument("--summarize", metavar="DIR", default=None,
                     help="only write the profiles/ summaries from rocprofv3 output in DIR")
+    ap.add_argument("--summarize-tags", default="f32",
+                    help="comma-separated profiled workloads to summarize (" + ",".join(PROFILE_RUNS) + ")")
+    ap.add_argument("--storage", choices=sorted(STORAGE_BYTES), default="f32",
+                    help="storage of the timed 128^3 droplet (the benchmark line: f32)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only time the 48-member batched sweep over --steps steps (profiling)")
     args = ap.parse_args()
     if args.precision:
         precision_study(args, args.precision)
         return
     if args.summarize:
-        summarize_profiles(args.summarize, args.size)
+        for tag in args.summarize_tags.split(","):
+            summarize_profiles(args.summarize, tag, args.size)
         return
     if args.tolman:
         tolman_sweep(args, args.tolman)
+        return
+    if args.batch_only:
+        batch_only(args)
         return
     if args.copy_calib:
         import torch

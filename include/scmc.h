@@ -349,6 +349,19 @@ int scmc_batch_autotune(scmc_batch *b, const char *cache_path, int *tile);
 /* Kernel design and tile in use by a handle. */
 int scmc_config(scmc_sim *s, int *kernel, int *tile);
 
+/* Measurement aid, not a step of the method: the streaming half of eq. lbm
+ * without its arithmetic.  Copies the 2*Q population planes of one of the
+ * handle's buffers into the other with the pull shifts, f_i(x) <- f_i(x -
+ * xi_i) (periodic), one site per lane and in the step's access pattern,
+ * reps >= 1 times (alternating the buffers), timed with events on the
+ * handle's stream; *us = mean microseconds per copy.  Every population is
+ * read and written once, as in a step, so 4*Q*s*N bytes / *us is the
+ * bandwidth ceiling of any step design that moves each population once (s
+ * = bytes per stored value).  The buffers then hold shifted copies: the
+ * handle's state is unset (SCMC_ESTATE until scmc_set_density or
+ * scmc_set_populations).  Synchronous. */
+int scmc_pull_copy(scmc_sim *s, int reps, double *us);
+
 /* Text of the last failure on a handle; with NULL, of the calling thread's
  * last scmc_step_static failure (or "NULL handle"). */
 const char *scmc_last_error(const scmc_sim *s);

@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "libscmc.so")
 SOURCES = [("step_kernels.hip", "step_kernels", []),
            ("fused_kernels.hip", "fused_kernels", []),
            ("obs_kernels.hip", "obs_kernels", []),
+           ("ceiling_kernels.hip", "ceiling_kernels", []),
            ("scmc_api.cpp", "scmc_api", [])]
 for _st in ("StoreF32", "StoreF16", "StoreBF16"):
     for _order in (4, 6):

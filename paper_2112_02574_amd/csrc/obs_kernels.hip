@@ -3,8 +3,9 @@
 // velocity field, the lattice pressure tensor on the droplet axis and the
 // transverse-averaged flat profiles (paper Sec. 2 eq. sm:pt and eq. bulkp,
 // Sec. 3 eq. gen_sigma, Sec. 4).  Every reduction runs in a fixed order
-// (per-thread sequential, then a shared-memory tree, then one final block),
-// so repeated calls on the same state give bitwise-identical results.
+// (per-thread sequential, then a butterfly across each wavefront's lanes and
+// the wavefronts in order, then one final block), so repeated calls on the
+// same state give bitwise-identical results.
 #include "site_ops.h"
 
 namespace scmc {
@@ -113,11 +114,35 @@ __device__ __forceinline__ double combine(int k, double a, double b) {
     return a + b;
 }
 
+// Deterministic reduction of NK values per thread over a block of NT
+// threads (linear thread index tid): a butterfly of cross-lane exchanges
+// inside each 64-wide wavefront (fixed partners, so every lane ends with the
+// same value whatever the hardware's scheduling), then thread 0 combines the
+// wavefronts' results in order.  The result is valid in thread 0.
+template <int NK, int NT, class Op>
+__device__ __forceinline__ void block_reduce(double (&v)[NK], double (&red)[NK][NT / 64], int tid,
+                                             Op op) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < NK; ++k) v[k] = op(k, v[k], __shfl_xor(v[k], off, 64));
+    if ((tid & 63) == 0)
+        for (int k = 0; k < NK; ++k) red[k][tid >> 6] = v[k];
+    __syncthreads();
+    if (tid == 0)
+        for (int k = 0; k < NK; ++k) {
+            double a = red[k][0];
+            for (int w = 1; w < NT / 64; ++w) a = op(k, a, red[k][w]);
+            v[k] = a;
+        }
+}
+__device__ __forceinline__ double add_op(int, double a, double b) { return a + b; }
+
 template <int D, int ORDER, class ST, int PSI>
 __global__ void __launch_bounds__(OB_THREADS)
     k_stats(Member m, const typename ST::T *__restrict__ src,
             const double *__restrict__ dens, double *__restrict__ partials) {
-    __shared__ double red[NSTAT][OB_THREADS];
+    __shared__ double red[NSTAT][OB_THREADS / 64];
     const int tid = threadIdx.y * OB_BX + threadIdx.x;
     const int x = blockIdx.x * OB_BX + threadIdx.x;
     const int y = blockIdx.y * OB_BY + threadIdx.y;
@@ -158,40 +183,26 @@ __global__ void __launch_bounds__(OB_THREADS)
         v[7] = sqrt(uu);
         v[8] = bad;
     }
-    for (int k = 0; k < NSTAT; ++k) red[k][tid] = v[k];
-    __syncthreads();
-    for (int h = OB_THREADS / 2; h > 0; h >>= 1) {
-        if (tid < h)
-            for (int k = 0; k < NSTAT; ++k)
-                red[k][tid] = combine(k, red[k][tid], red[k][tid + h]);
-        __syncthreads();
-    }
+    block_reduce<NSTAT, OB_THREADS>(v, red, tid, combine);
     if (tid == 0) {
         const long b = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x +
                        blockIdx.x;
-        for (int k = 0; k < NSTAT; ++k) partials[b * NSTAT + k] = red[k][0];
+        for (int k = 0; k < NSTAT; ++k) partials[b * NSTAT + k] = v[k];
     }
 }
 
 __global__ void __launch_bounds__(256)
     k_stats_final(const double *__restrict__ partials, int nblocks,
                   double *__restrict__ out) {
-    __shared__ double red[NSTAT][256];
+    __shared__ double red[NSTAT][256 / 64];
     const int tid = threadIdx.x;
     double v[NSTAT] = {0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
     for (int b = tid; b < nblocks; b += 256)
         for (int k = 0; k < NSTAT; ++k)
             v[k] = combine(k, v[k], partials[(long)b * NSTAT + k]);
-    for (int k = 0; k < NSTAT; ++k) red[k][tid] = v[k];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h)
-            for (int k = 0; k < NSTAT; ++k)
-                red[k][tid] = combine(k, red[k][tid], red[k][tid + h]);
-        __syncthreads();
-    }
+    block_reduce<NSTAT, 256>(v, red, tid, combine);
     if (tid == 0)
-        for (int k = 0; k < NSTAT; ++k) out[k] = red[k][0];
+        for (int k = 0; k < NSTAT; ++k) out[k] = v[k];
 }
 
 template <int D, int ORDER, class ST, int PSI>
@@ -271,7 +282,7 @@ constexpr int LINE_THREADS = 256;
 template <int D, int ORDER, int PSI>
 __global__ void __launch_bounds__(LINE_THREADS)
     k_line(Member m, const double *__restrict__ dens, double *__restrict__ out) {
-    __shared__ double red[LINE_THREADS];
+    __shared__ double red[1][LINE_THREADS / 64];
     const int cx = m.nx / 2, cy = m.ny / 2, cz = D == 3 ? m.nz / 2 : 0;
     const int rmax = m.nx / 2;
     const int tid = threadIdx.x;
@@ -300,16 +311,12 @@ __global__ void __launch_bounds__(LINE_THREADS)
             (pow(b, mexp + 2) - pow(a, mexp + 2)) / (mexp + 2) - a * I0;
         acc += g0 * I0 + (g1 - g0) * I1;
     }
-    red[tid] = acc;
-    __syncthreads();
-    for (int h = LINE_THREADS / 2; h > 0; h >>= 1) {
-        if (tid < h) red[tid] += red[tid + h];
-        __syncthreads();
-    }
+    double v[1] = {acc};
+    block_reduce<1, LINE_THREADS>(v, red, tid, add_op);
     if (tid == 0) {
         out[3 * (rmax + 1)] = bulk_pressure<PSI>(m, dens[sc], dens[m.N + sc]);
         out[3 * (rmax + 1) + 1] = Pout;
-        out[3 * (rmax + 1) + 2] = red[0];
+        out[3 * (rmax + 1) + 2] = v[0];
     }
 }
 
@@ -318,7 +325,7 @@ constexpr int FLAT_THREADS = 256;
 template <int D, int ORDER, int PSI>
 __global__ void __launch_bounds__(FLAT_THREADS)
     k_flat(Member m, const double *__restrict__ dens, double *__restrict__ out) {
-    __shared__ double rn[FLAT_THREADS], rt[FLAT_THREADS];
+    __shared__ double red[2][FLAT_THREADS / 64];
     const int x = blockIdx.x, tid = threadIdx.x;
     const int ntr = m.ny * m.nz;
     double pn = 0, pt = 0;
@@ -328,19 +335,11 @@ __global__ void __launch_bounds__(FLAT_THREADS)
         pn += P[0];
         pt += P[1];
     }
-    rn[tid] = pn;
-    rt[tid] = pt;
-    __syncthreads();
-    for (int h = FLAT_THREADS / 2; h > 0; h >>= 1) {
-        if (tid < h) {
-            rn[tid] += rn[tid + h];
-            rt[tid] += rt[tid + h];
-        }
-        __syncthreads();
-    }
+    double v[2] = {pn, pt};
+    block_reduce<2, FLAT_THREADS>(v, red, tid, add_op);
     if (tid == 0) {
-        out[x] = rn[0] / ntr;
-        out[m.nx + x] = rt[0] / ntr;
+        out[x] = v[0] / ntr;
+        out[m.nx + x] = v[1] / ntr;
     }
 }
 
@@ -397,7 +396,7 @@ __global__ void __launch_bounds__(OB_THREADS)
     k_monitor(Member m, int dim, const double *__restrict__ dens,
               const double *__restrict__ u, const double *__restrict__ u0, int rich,
               double n_out, double *__restrict__ partials) {
-    __shared__ double red[NMON][OB_THREADS];
+    __shared__ double red[NMON][OB_THREADS / 64];
     const int tid = threadIdx.y * OB_BX + threadIdx.x;
     const int x = blockIdx.x * OB_BX + threadIdx.x;
     const int y = blockIdx.y * OB_BY + threadIdx.y;
@@ -413,36 +412,24 @@ __global__ void __launch_bounds__(OB_THREADS)
         v[3] = ex * (y - m.ny / 2);
         v[4] = dim == 3 ? ex * (z - m.nz / 2) : 0.0;
     }
-    for (int k = 0; k < NMON; ++k) red[k][tid] = v[k];
-    __syncthreads();
-    for (int h = OB_THREADS / 2; h > 0; h >>= 1) {
-        if (tid < h)
-            for (int k = 0; k < NMON; ++k) red[k][tid] += red[k][tid + h];
-        __syncthreads();
-    }
+    block_reduce<NMON, OB_THREADS>(v, red, tid, add_op);
     if (tid == 0) {
         const long b = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        for (int k = 0; k < NMON; ++k) partials[b * NMON + k] = red[k][0];
+        for (int k = 0; k < NMON; ++k) partials[b * NMON + k] = v[k];
     }
 }
 
 __global__ void __launch_bounds__(256)
     k_monitor_final(const double *__restrict__ partials, int nblocks,
                     double *__restrict__ out) {
-    __shared__ double red[NMON][256];
+    __shared__ double red[NMON][256 / 64];
     const int tid = threadIdx.x;
     double v[NMON] = {0, 0, 0, 0, 0};
     for (int b = tid; b < nblocks; b += 256)
         for (int k = 0; k < NMON; ++k) v[k] += partials[(long)b * NMON + k];
-    for (int k = 0; k < NMON; ++k) red[k][tid] = v[k];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h)
-            for (int k = 0; k < NMON; ++k) red[k][tid] += red[k][tid + h];
-        __syncthreads();
-    }
+    block_reduce<NMON, 256>(v, red, tid, add_op);
     if (tid == 0)
-        for (int k = 0; k < NMON; ++k) out[k] = red[k][0];
+        for (int k = 0; k < NMON; ++k) out[k] = v[k];
 }
 
 hipError_t launch_monitor(const Member &m, int dim, const double *dens64, const double *u,

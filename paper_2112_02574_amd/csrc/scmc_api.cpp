@@ -1334,6 +1334,35 @@ int scmc_curvature_fit(int n, const double *curvature, const double *sigma, doub
     return SCMC_OK;
 }
 
+int scmc_pull_copy(scmc_sim *s, int reps, double *us) {
+    if (!s || !us || reps < 1) return SCMC_EINVAL;
+    Common &c = s->c;
+    const Lat &L = s->lat;
+    const int bytes = (int)storage_bytes(L.p.storage);
+    Member m = L.m;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    hipError_t e = launch_pull_copy(L.dim, bytes, m, c.pop[0], c.pop[1], c.stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, c.stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = launch_pull_copy(L.dim, bytes, m, c.pop[r & 1], c.pop[1 - (r & 1)], c.stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, c.stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // the buffers now hold shifted copies, not a state of the method
+    c.initialized = false;
+    c.step = 0;
+    c.cur = 0;
+    s->have_prev = false;
+    if (e != hipSuccess) return fail(c, SCMC_EDEVICE, "pull copy: %s", hipGetErrorString(e));
+    *us = 1e3 * ms / reps;
+    return SCMC_OK;
+}
+
 int scmc_config(scmc_sim *s, int *kernel, int *tile) {
     if (!s) return SCMC_EINVAL;
     if (kernel)

@@ -107,6 +107,12 @@ bool node_batch_two_pass(const StepKey &k, int grid, NodeLaunch *dens_node,
 bool node_batch_fused(const StepKey &k, const int *tile, int grid,
                       NodeLaunch *node);
 
+// ---- bandwidth ceiling (ceiling_kernels.hip): the 2Q population planes of
+// src copied to dst with the pull shifts, one site per lane; elements of
+// `bytes` bytes (8, 4 or 2)
+hipError_t launch_pull_copy(int dim, int bytes, const Member &m, const void *src, void *dst,
+                            hipStream_t st);
+
 // ---- FP64 observable kernels (obs_kernels.hip)
 // dens64[J][s] = sum_i f_i^J of the current state (pulled, decoded, FP64)
 hipError_t launch_density64(const StepKey &k, const Member &m, const void *pop,

@@ -121,6 +121,7 @@ _SYMBOLS = {
     "scmc_autotune": ([ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "scmc_batch_autotune": ([ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "scmc_config": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "scmc_pull_copy": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "scmc_convergence_check": ([ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.POINTER(Convergence)], ctypes.c_int),
     "scmc_run_to_convergence": ([ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
@@ -392,6 +393,11 @@ class Sim:
         t = (ctypes.c_int * 3)()
         self._check(lib().scmc_config(self.h, ctypes.byref(k), t), "scmc_config")
         return k.value, tuple(t)
+
+    def scmc_pull_copy(self, reps):
+        us = ctypes.c_double()
+        self._check(lib().scmc_pull_copy(self.h, int(reps), ctypes.byref(us)), "scmc_pull_copy")
+        return us.value
 
     def scmc_autotune(self, cache_path=None):
         t = (ctypes.c_int * 3)()
