@@ -314,10 +314,13 @@ int scmc_flat_equilibrium(const scmc_problem *p, int lx, const double *guess,
                           size_t ws_bytes, void *stream, double *out,
                           int64_t *steps);
 
-/* Many independent lattices advanced by one persistent launch per step
- * (the paper's sweep over droplet sizes and couplings, Sec. 4).  Members may
- * differ in size and couplings; they must share lattice, stencil, tau and
- * storage.  Member calls take the member index i. */
+/* Many independent lattices advanced together over one tile list (the
+ * paper's sweep over droplet sizes and couplings, Sec. 4).  The moment
+ * two-pass runs the members in chunks, one workgroup per 256-site tile, pass
+ * 2 of a chunk in the same launch as pass 1 of the next; the fused designs
+ * run one persistent launch per step.  Members may differ in size and
+ * couplings; they must share lattice, stencil, tau and storage.  Member calls
+ * take the member index i. */
 typedef struct scmc_batch scmc_batch;
 int scmc_batch_workspace_bytes(const scmc_problem *ps, int count, size_t *out);
 int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
@@ -335,7 +338,8 @@ int scmc_batch_get_populations(scmc_batch *b, int i, double *f, int64_t *step);
 int scmc_batch_stats_get(scmc_batch *b, int i, scmc_stats *out);
 int scmc_batch_observables(scmc_batch *b, int i, int kind, double R0,
                            scmc_obs *out, double *PN, double *PT);
-/* Tile (x, y, z-chunk) and persistent grid size in use. */
+/* Tile (x, y, z-chunk) and the fused designs' persistent grid (workgroups
+ * before the clamp to those the device holds at once). */
 int scmc_batch_config(scmc_batch *b, int *tile, int *grid);
 
 /* Autotuner: times each candidate fused-kernel tile on a scratch state in

@@ -712,7 +712,9 @@ hipError_t FusedOps<ST, ORDER>::launch_batch(const StepKey &k,
     dispatch(k, tile, [&](auto Pc, auto Rc, auto TXc, auto TYc) {
         constexpr int P = decltype(Pc)::value, RP = decltype(Rc)::value;
         constexpr int TXv = decltype(TXc)::value, TYv = decltype(TYc)::value;
-        hipLaunchKernelGGL((kb_fused<TXv, TYv, ORDER, ST, P, RP>), dim3(grid),
+        const void *f = (const void *)&kb_fused<TXv, TYv, ORDER, ST, P, RP>;
+        hipLaunchKernelGGL((kb_fused<TXv, TYv, ORDER, ST, P, RP>),
+                           dim3(std::min(grid, resident_blocks(f, TXv * TYv))),
                            dim3(TXv, TYv), 0, st, d_members, d_tiles, ntiles,
                            (const T *)src, (T *)dst, tile[2]);
         err = hipGetLastError();
@@ -727,7 +729,7 @@ bool FusedOps<ST, ORDER>::node_batch(const StepKey &k, const int *tile,
         constexpr int P = decltype(Pc)::value, RP = decltype(Rc)::value;
         constexpr int TXv = decltype(TXc)::value, TYv = decltype(TYc)::value;
         node->func = (void *)&kb_fused<TXv, TYv, ORDER, ST, P, RP>;
-        node->grid = dim3(grid);
+        node->grid = dim3(std::min(grid, resident_blocks(node->func, TXv * TYv)));
         node->block = dim3(TXv, TYv);
         node->shmem = 0;
     });

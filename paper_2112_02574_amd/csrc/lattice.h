@@ -219,6 +219,13 @@ __host__ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
     return v;
 }
 
+// The same rounding in one instruction: gfx950 converts binary32 to bfloat16
+// in hardware, to nearest even in the default rounding mode, keeping
+// subnormals (the FP32 denormal mode of HIP code) and quieting NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16_dev(float v) {
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
 struct StoreBF16 {
     using T = uint16_t;
     using R = float;
@@ -227,13 +234,13 @@ struct StoreBF16 {
         return bf16_to_f32(v) + ref;
     }
     __device__ __forceinline__ static T to_raw(R v, R ref) {
-        return f32_to_bf16_rne(v - ref);
+        return f32_to_bf16_dev(v - ref);
     }
     __device__ __forceinline__ static R load(const T *p, long i, R ref) {
         return bf16_to_f32(p[i]) + ref;
     }
     __device__ __forceinline__ static void store(T *p, long i, R v, R ref) {
-        const T h = f32_to_bf16_rne(v - ref);
+        const T h = f32_to_bf16_dev(v - ref);
         __builtin_nontemporal_store(h, p + i);
     }
     // node storage: bfloat16 has the binary32 exponent range, no scale
@@ -245,7 +252,7 @@ struct StoreBF16 {
     __device__ __forceinline__ static T to_raw_sr(R v, R ref, unsigned r) {
         const float x = v - ref;
         const uint32_t u = __float_as_uint(x);
-        if ((u & 0x7f800000u) == 0x7f800000u) return f32_to_bf16_rne(x);
+        if ((u & 0x7f800000u) == 0x7f800000u) return f32_to_bf16_dev(x);
         return (uint16_t)((u + (r & 0xFFFFu)) >> 16);
     }
 };

@@ -210,6 +210,12 @@ struct scmc_sim {
     int64_t prev_step = 0;
 };
 
+// One launch of the batched two-pass: pass 1 or 2 over tiles [t0, t0 + n),
+// one workgroup per tile.
+struct BatchOp {
+    int pass, t0, n;
+};
+
 struct scmc_batch {
     Common c;
     std::vector<Lat> lats;
@@ -219,11 +225,9 @@ struct scmc_batch {
     int ntiles_cap = 0;  // tile-list capacity planned in the workspace
     int grid = 0;
     std::vector<bool> member_set;
-    // The moment two-pass runs the tile list in chunks of whole members, each
-    // chunk's pass 2 right after its pass 1, so that the chunk's moment field
-    // (24 B per site in FP32) is still in the caches; chunks[k] is the first
-    // tile of chunk k and chunks.back() == ntiles.
-    std::vector<int> chunks;
+    // The launches of one two-pass step (batch_set_ops); empty for the fused
+    // designs, which run the whole list in one persistent launch.
+    std::vector<BatchOp> ops;
 };
 
 namespace {
@@ -835,12 +839,11 @@ int direct_step_batch(scmc_batch *b) {
     if (c.kernel == SCMC_KERNEL_FUSED) {
         e = launch_batch_fused(c.key, b->d_members, b->d_tiles, b->ntiles, src, dst, c.tile,
                                b->grid, c.stream);
-    } else {
-        for (size_t k = 0; e == hipSuccess && k + 1 < b->chunks.size(); ++k) {
-            const int t0 = b->chunks[k], nt = b->chunks[k + 1] - t0;
-            e = launch_batch_two_pass(c.key, b->d_members, b->d_tiles + t0, nt, src, dst,
-                                      c.dens, std::min(b->grid, nt), c.stream);
-        }
+    }
+    for (size_t k = 0; e == hipSuccess && k < b->ops.size(); ++k) {
+        const BatchOp &o = b->ops[k];
+        e = launch_batch_two_pass(c.key, b->d_members, b->d_tiles + o.t0, o.n, src, dst, c.dens,
+                                  o.n, c.stream, o.pass);
     }
     if (e != hipSuccess)
         return fail(c, SCMC_EDEVICE, "batch step launch: %s",
@@ -862,11 +865,12 @@ struct ArgPack {
     int tile[3];
 };
 
-// A batch runs its tile list as the chunks [chunks[j], chunks[j + 1]) (one
-// chunk {0, 0} for a single lattice, {0, ntiles} for the fused designs).
+// A single lattice passes chunks {0, 0}; a batch either its two-pass
+// launches (ops) or, for the fused designs, chunks {0, ntiles}.
 int build_graph(Common &c, int k, int par, bool batch, const Member &m,
                 const Member *d_members, const Tile *d_tiles,
-                const std::vector<int> &chunks, int grid) {
+                const std::vector<int> &chunks, int grid,
+                const std::vector<BatchOp> *ops = nullptr) {
     hipGraph_t g = nullptr;
     HIPCHK(c, hipGraphCreate(&g, 0));
     hipGraphNode_t prev = nullptr;
@@ -886,8 +890,37 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
     };
     int cur = par, rc = SCMC_OK;
     for (int t = 0; t < k && !rc; ++t) {
+        if (ops) {  // the two-pass launches of direct_step_batch
+            NodeLaunch dn{}, sn{};
+            if (!node_batch_two_pass(c.key, 1, &dn, &sn)) {
+                rc = fail(c, SCMC_EUNSUPPORTED, "no graph node for this kernel");
+                break;
+            }
+            const Member *dm = d_members;
+            const Tile *dt = d_tiles;
+            int nt = 0;
+            const void *srcv = c.pop[cur];
+            void *dstv = c.pop[1 - cur];
+            void *densv = c.dens;
+            std::vector<void *> dargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
+                                         (void *)&densv};
+            std::vector<void *> sargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
+                                         (void *)&dstv, (void *)&densv};
+            for (const BatchOp &o : *ops) {
+                if (rc) break;
+                dt = d_tiles + o.t0;
+                nt = o.n;
+                NodeLaunch nl = o.pass == 1 ? dn : sn;
+                nl.grid = dim3(nt);  // one workgroup per tile
+                rc = add(nl, o.pass == 1 ? dargs : sargs);
+            }
+            cur ^= 1;
+            continue;
+        }
         for (size_t ch = 0; ch + 1 < chunks.size() && !rc; ++ch) {
             const int ntiles = chunks[ch + 1] - chunks[ch];
+            // persistent fused launches: at most `grid` workgroups (clamped to
+            // the resident count)
             const int cgrid = batch ? std::min(grid, ntiles) : grid;
             NodeLaunch dn{}, sn{};
             const bool ok = batch ? (fused ? node_batch_fused(c.key, c.tile, cgrid, &sn)
@@ -922,13 +955,35 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
             const std::vector<SlabOp> slabs =
                 batch || fused ? std::vector<SlabOp>() : slab_schedule(c.key, m);
             if (!slabs.empty()) {  // the moment two-pass in z-slabs, as launch_two_pass
+                NodeLaunch pn{};
+                Member mv1 = ms;
+                int nb2 = 0, nb1 = 0;
+                std::vector<void *> pargs = {(void *)&mv, (void *)&mv1, (void *)&nb2,
+                                                   (void *)&nb1, (void *)&srcv, (void *)&dstv,
+                                                   (void *)&densv};
                 for (const SlabOp &o : slabs) {
-                    NodeLaunch nl = o.pass == 1 ? dn : sn;
-                    nl.grid = dim3(linear_blocks(m, o.nz, (int)nl.block.x));
+                    if (rc) break;
                     mv = ms;
                     mv.zoff = o.z0;
                     mv.znum = o.nz;
-                    if (!rc) rc = add(nl, o.pass == 1 ? dargs : sargs);
+                    if (o.pass == 3) {
+                        if (!pn.func && !node_slab_pair(c.key, &pn)) {
+                            rc = fail(c, SCMC_EUNSUPPORTED, "no graph node for the slab pair");
+                            break;
+                        }
+                        mv1 = ms;
+                        mv1.zoff = o.z1;
+                        mv1.znum = o.n1;
+                        nb2 = linear_blocks(m, o.nz, (int)pn.block.x);
+                        nb1 = linear_blocks(m, o.n1, (int)pn.block.x);
+                        NodeLaunch nl = pn;
+                        nl.grid = dim3(nb2 + nb1);
+                        rc = add(nl, pargs);
+                        continue;
+                    }
+                    NodeLaunch nl = o.pass == 1 ? dn : sn;
+                    nl.grid = dim3(linear_blocks(m, o.nz, (int)nl.block.x));
+                    rc = add(nl, o.pass == 1 ? dargs : sargs);
                 }
                 continue;
             }
@@ -1460,16 +1515,49 @@ int scmc_flat_equilibrium(const scmc_problem *p, int lx, const double *guess,
 }
 
 // ------------------------------------------------------------------ batch
+// Chunks of whole members for the batched moment two-pass (see scmc_batch),
+// in the order of the two-pass tile list.  A member whose moment field
+// reaches kBatchChunkBytes is a chunk of its own; the others join chunks, in
+// their given order, until a chunk's moment fields would pass
+// kBatchChunkBytes.
+static constexpr size_t kBatchChunkBytes = (size_t)48 << 20;
+
+static std::vector<std::vector<int>> two_pass_chunks(const std::vector<scmc_problem> &ps) {
+    std::vector<std::vector<int>> out;
+    size_t bytes = 0;
+    bool open = false;  // the last chunk takes more members
+    for (int i = 0; i < (int)ps.size(); ++i) {
+        const scmc_problem &p = ps[i];
+        const size_t mb = (size_t)6 * p.nx * p.ny * p.nz * real_bytes(p.storage);
+        if (mb >= kBatchChunkBytes) {
+            out.push_back({i});
+            open = false;
+            continue;
+        }
+        if (!open || bytes + mb > kBatchChunkBytes) {
+            out.push_back({});
+            bytes = 0;
+            open = true;
+        }
+        out.back().push_back(i);
+        bytes += mb;
+    }
+    return out;
+}
+
 static int batch_tiles(const std::vector<scmc_problem> &ps, int kernel,
                        const int *tile, std::vector<Tile> *out) {
     out->clear();
+    if (kernel != SCMC_KERNEL_FUSED) {  // runs of 256 consecutive sites, chunk by chunk
+        for (const std::vector<int> &chunk : two_pass_chunks(ps))
+            for (int i : chunk) {
+                const int N = ps[i].nx * ps[i].ny * ps[i].nz;
+                for (int s0 = 0; s0 < N; s0 += 256) out->push_back({i, s0, 0, 0});
+            }
+        return (int)out->size();
+    }
     for (int i = 0; i < (int)ps.size(); ++i) {
         const scmc_problem &p = ps[i];
-        if (kernel != SCMC_KERNEL_FUSED) {  // runs of 256 consecutive sites
-            const int N = p.nx * p.ny * p.nz;
-            for (int s0 = 0; s0 < N; s0 += 256) out->push_back({i, s0, 0, 0});
-            continue;
-        }
         for (int z = 0; z < p.nz; z += tile[2])
             for (int y = 0; y < p.ny; y += tile[1])
                 for (int x = 0; x < p.nx; x += tile[0]) out->push_back({i, x, y, z});
@@ -1477,33 +1565,34 @@ static int batch_tiles(const std::vector<scmc_problem> &ps, int kernel,
     return (int)out->size();
 }
 
-// Chunks of whole members for the batched moment two-pass (see scmc_batch):
-// members join a chunk until its moment fields would pass kBatchChunkBytes.
-// The fused designs, the other two-pass forms and stochastic rounding (whose
-// step counter advances at the first tile of a launch) run the whole list.
-static constexpr size_t kBatchChunkBytes = (size_t)48 << 20;
-
-static void batch_set_chunks(scmc_batch *b) {
+// The launches of a two-pass step: pass 1 and then pass 2 of each chunk in
+// turn, so that pass 2 finds the chunk's moments still cached.  (Sharing a
+// launch between pass 2 of one chunk and pass 1 of the next measured no
+// faster.)  The fused designs (one persistent launch), the density two-pass
+// and stochastic rounding (whose step counter advances at the first tile of
+// pass 1) run pass 1 and then pass 2 over the whole list.
+static void batch_set_ops(scmc_batch *b) {
     const Common &c = b->c;
-    bool chunked = c.kernel != SCMC_KERNEL_FUSED && c.key.mom;
+    b->ops.clear();
+    if (c.kernel == SCMC_KERNEL_FUSED) return;
+    bool chunked = c.key.mom;
     for (const Lat &L : b->lats) chunked = chunked && !L.m.sr;
-    std::vector<int> ch = {0};
+    std::vector<BatchOp> ops;
     if (chunked) {
+        std::vector<scmc_problem> ps;
+        for (const Lat &L : b->lats) ps.push_back(L.p);
         int t = 0;
-        size_t bytes = 0;
-        for (const Lat &L : b->lats) {
-            const size_t mb = (size_t)6 * L.m.N * real_bytes(L.p.storage);
-            if (t > ch.back() && bytes + mb > kBatchChunkBytes) {
-                ch.push_back(t);
-                bytes = 0;
-            }
-            t += (L.m.N + 255) / 256;  // the two-pass tiles of batch_tiles
-            bytes += mb;
+        for (const std::vector<int> &chunk : two_pass_chunks(ps)) {
+            int n = 0;
+            for (int i : chunk) n += (b->lats[i].m.N + 255) / 256;  // tiles of batch_tiles
+            ops.push_back({1, t, n});
+            ops.push_back({2, t, n});
+            t += n;
         }
-        if (t != b->ntiles) ch = {0};
+        if (t != b->ntiles) ops.clear();
     }
-    ch.push_back(b->ntiles);
-    b->chunks = ch;
+    if (ops.empty()) ops = {{1, 0, b->ntiles}, {2, 0, b->ntiles}};
+    b->ops = ops;
 }
 
 // Tile-list capacity: enough for the current design, for the smallest fused
@@ -1621,7 +1710,7 @@ int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
             ncu = prop.multiProcessorCount;
     }
     b->grid = std::min(b->ntiles, ncu * 8);
-    batch_set_chunks(b);
+    batch_set_ops(b);
     hipError_t e = hipMemcpyAsync(b->d_members, ms.data(),
                                   ms.size() * sizeof(Member),
                                   hipMemcpyHostToDevice, c.stream);
@@ -1681,8 +1770,10 @@ int scmc_batch_step(scmc_batch *b, int64_t nsteps) {
     return run_steps(
         c, nsteps, [&] { return direct_step_batch(b); },
         [&](int par) {
-            return build_graph(c, c.graph_k, par, true, Member{}, b->d_members,
-                               b->d_tiles, b->chunks, b->grid);
+            const std::vector<int> whole = {0, b->ntiles};
+            return build_graph(c, c.graph_k, par, true, Member{}, b->d_members, b->d_tiles,
+                               whole, b->grid,
+                               c.kernel == SCMC_KERNEL_FUSED ? nullptr : &b->ops);
         });
 }
 
@@ -1943,7 +2034,7 @@ int scmc_batch_autotune(scmc_batch *b, const char *cache_path, int *tile) {
             return fail(c, SCMC_ENOSPACE, "tile list larger than planned");
         apply(c, cand);
         b->ntiles = nt;
-        batch_set_chunks(b);
+        batch_set_ops(b);
         HIPCHK(c, hipMemcpyAsync(b->d_tiles, tiles.data(), nt * sizeof(Tile),
                                  hipMemcpyHostToDevice, c.stream));
         HIPCHK(c, hipStreamSynchronize(c.stream));

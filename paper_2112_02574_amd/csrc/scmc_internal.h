@@ -73,10 +73,19 @@ hipError_t launch_fused(const StepKey &k, const Member &m, const void *src,
                         void *dst, const int *tile, hipStream_t st);
 bool fused_supported(const StepKey &k, const int *tile);
 // Batched persistent launches over a tile list (device arrays).
+// Workgroups of kernel f (threads each, shmem bytes of dynamic LDS) that the
+// current device holds at once.  The fused batched launches are persistent
+// loops over a tile list and use at most that many: surplus workgroups would
+// start only after others had run their whole share of the list.  (The
+// two-pass batched launches run one workgroup per 256-site tile.)
+int resident_blocks(const void *f, int threads, unsigned shmem = 0);
+// grid: workgroups; one per tile runs each tile once.  passes: 1 = pass 1
+// only, 2 = pass 2 only, 3 = both
 hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
                                  const Tile *d_tiles, int ntiles,
                                  const void *src, void *dst, void *dens,
-                                 int grid, hipStream_t st);
+                                 int grid, hipStream_t st, int passes = 3);
+
 hipError_t launch_batch_fused(const StepKey &k, const Member *d_members,
                               const Tile *d_tiles, int ntiles, const void *src,
                               void *dst, const int *tile, int grid,
@@ -91,10 +100,14 @@ struct NodeLaunch {
 // caches runs in z-slabs: pass 2 of a slab follows pass 1 of the next one, so
 // the moments it gathers are still cached.  Empty: one launch per pass.
 struct SlabOp {
-    int pass;  // 1 or 2
+    int pass;    // 1 or 2; 3: pass 2 over [z0, z0 + nz) and, in the same
+                 // launch (k_slab_pair), pass 1 over [z1, z1 + n1)
     int z0, nz;
+    int z1 = 0, n1 = 0;
 };
 std::vector<SlabOp> slab_schedule(const StepKey &k, const Member &m);
+// the kernel of the pass-3 slab launches (grid and block set per launch)
+bool node_slab_pair(const StepKey &k, NodeLaunch *node);
 // Blocks of blk linearly numbered sites that cover znum planes of m.
 int linear_blocks(const Member &m, int znum, int blk);
 

@@ -103,12 +103,13 @@ __device__ __forceinline__ void site_density(const R (&f)[2][Lattice<D>::Q],
 }
 
 // Stencil sums of eq. sc_force around site (x, y, z), with the stencil
-// concentrations returned by fetch(t, n_A, n_B) (t = linear site index), then
-// the force on both components.  The stencil is point-symmetric, so the sum
-// runs over pairs (e, -e): W e (Phi(x + e) - Phi(x - e)).  The difference is
-// exactly odd under e -> -e and the pair sums are accumulated in FP64 (the
-// order-free sums above).
-template <int D, int ORDER, int PSI, class R, class Fetch>
+// concentrations returned by fetch(t, n_A, n_B) (t = linear site index times
+// UNIT, e.g. a byte offset into an array of (n_A, n_B) pairs), then the force
+// on both components.  The stencil is point-symmetric, so the sum runs over
+// pairs (e, -e): W e (Phi(x + e) - Phi(x - e)).  The difference is exactly
+// odd under e -> -e and the pair sums are accumulated in FP64 (the order-free
+// sums above).
+template <int D, int ORDER, int PSI, class R, int UNIT = 1, class Fetch>
 __device__ __forceinline__ void site_force_fn(const Member &m, int x, int y, int z,
                                               R nA, R nB, R (&FA)[3], R (&FB)[3],
                                               Fetch &&fetch) {
@@ -122,9 +123,9 @@ __device__ __forceinline__ void site_force_fn(const Member &m, int x, int y, int
     int xo[5], yo[5], zo[5];
 #pragma unroll
     for (int d = -2; d <= 2; ++d) {
-        xo[d + 2] = wrap1(x + d, m.nx);
-        yo[d + 2] = wrap1(y + d, m.ny) * m.nx;
-        zo[d + 2] = D == 3 ? wrap1(z + d, m.nz) * (m.nx * m.ny) : 0;
+        xo[d + 2] = wrap1(x + d, m.nx) * UNIT;
+        yo[d + 2] = wrap1(y + d, m.ny) * (m.nx * UNIT);
+        zo[d + 2] = D == 3 ? wrap1(z + d, m.nz) * (m.nx * m.ny * UNIT) : 0;
     }
 #pragma unroll
     for (int a = S::NE / 2; a < S::NE; ++a) {
@@ -132,7 +133,7 @@ __device__ __forceinline__ void site_force_fn(const Member &m, int x, int y, int
         const int ex = T.e[a][0], ey = T.e[a][1], ez = T.e[a][2];
         const int tp = zo[2 + ez] + yo[2 + ey] + xo[2 + ex];
         const int tm = zo[2 - ez] + yo[2 - ey] + xo[2 - ex];
-        R pAt, pBt, mAt, mBt;  // N < 2^31 (validated)
+        R pAt, pBt, mAt, mBt;  // N * UNIT < 2^31 (the callers' forms)
         fetch(tp, pAt, pBt);
         fetch(tm, mAt, mBt);
         const R dA = pAt - mAt, dB = pBt - mBt;

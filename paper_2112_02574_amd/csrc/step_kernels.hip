@@ -18,6 +18,9 @@
 // + 2Q writes of populations plus 24 B of moments each way (FP32), instead of
 // 4Q reads + 2Q writes.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "fused_impl.h"  // FusedGeom, lds_force, halo_pos, xcd_remap
@@ -49,15 +52,20 @@ __device__ __forceinline__ bool tile_site(const Member &m, const Tile &tl, int &
 // of larger lattices runs blocks of 512 (SLAB_BLOCK).
 constexpr int LIN_BLOCK = 256, SLAB_BLOCK = 512;
 template <int BLK>
-__device__ __forceinline__ bool linear_site(const Member &m, int &x, int &y, int &z) {
+__device__ __forceinline__ bool linear_site_at(const Member &m, int block, int &x, int &y,
+                                               int &z) {
     const int nxy = m.nx * m.ny;
-    const int s = m.zoff * nxy + blockIdx.x * BLK + threadIdx.x;
+    const int s = m.zoff * nxy + block * BLK + threadIdx.x;
     if (s >= (m.zoff + m.znum) * nxy) return false;
     z = s / nxy;
     const int r = s - z * nxy;
     y = r / m.nx;
     x = r - y * m.nx;
     return true;
+}
+template <int BLK>
+__device__ __forceinline__ bool linear_site(const Member &m, int &x, int &y, int &z) {
+    return linear_site_at<BLK>(m, blockIdx.x, x, y, z);
 }
 
 template <int D, class ST>
@@ -229,12 +237,18 @@ __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopB
     for (int c = 0; c < 3; ++c) mm[2 + c] = base[(2 + c) * (long)m.N + s];
     unpack_rem<R>(reinterpret_cast<const unsigned *>(base + 5 * (long)m.N)[s], mm);
     R FA[3], FB[3];
-    site_force_fn<3, ORDER, PSI, R>(m, x, y, z, own.x, own.y, FA, FB,
-                                    [&](int t, R &a, R &b) {
-                                        const Pair<R> q = pairs[t];
-                                        a = q.x;
-                                        b = q.y;
-                                    });
+    // stencil pairs through a buffer descriptor with 32-bit byte offsets
+    // (8 N < 2^31 in these forms): no 64-bit address arithmetic per neighbour
+    static_assert(sizeof(Pair<R>) == 8, "FP32 pairs");
+    const __amdgpu_buffer_rsrc_t pr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)pairs, (short)0, m.N * 8, BUF_DATA_FORMAT_32);
+    site_force_fn<3, ORDER, PSI, R, 8>(
+        m, x, y, z, own.x, own.y, FA, FB, [&](int t, R &a, R &b) {
+            const auto q = __builtin_amdgcn_raw_buffer_load_b64(pr, t, 0, 0);
+            const unsigned qa = q[0], qb = q[1];  // scalars before the cast
+            a = __uint_as_float(qa);
+            b = __uint_as_float(qb);
+        });
     const int voff = s * (int)sizeof(T);
     if constexpr (NODE) {
         float2 r;
@@ -349,6 +363,45 @@ __global__ void __launch_bounds__(BLK)
     int x, y, z;
     if (linear_site<BLK>(m, x, y, z))
         collide_mom_site_buf<ORDER, ST, PSI, NODE>(m, db, mom, x, y, z);
+}
+
+// Block b of a launch that runs n2 blocks of pass 2 and n1 of pass 1: groups
+// of 8 consecutive blocks alternate between the passes while
+// both last, so both spread over every XCD (workgroups go round-robin over
+// the 8 XCDs) and every CU mixes the two; the rest of the longer pass
+// follows.  Sets p2 and the unit's index within its pass.
+__device__ __forceinline__ void pair_unit(int b, int n2, int n1, bool &p2, int &i) {
+    const int m8 = (min(n1, n2) / 8) * 8;
+    if (b < 2 * m8) {
+        p2 = ((b >> 3) & 1) == 0;
+        i = ((b >> 4) << 3) | (b & 7);
+    } else {
+        b -= 2 * m8;
+        p2 = b < n2 - m8;
+        i = m8 + (p2 ? b : b - (n2 - m8));
+    }
+}
+
+// One launch of the slab schedule that runs pass 2 over the planes of m2 and
+// pass 1 over those of m1 (a later slab, whose moments pass 2 does not read,
+// from the source buffer, which pass 2 does not write): nb2 and nb1 blocks of
+// BLK sites.
+template <int ORDER, class ST, int PSI, int BLK, bool NODE = false>
+__global__ void __launch_bounds__(BLK)
+    k_slab_pair(Member m2, Member m1, int nb2, int nb1, const typename ST::T *__restrict__ src,
+                typename ST::T *__restrict__ dst, typename ST::R *__restrict__ mom) {
+    bool p2;
+    int bi;
+    pair_unit(blockIdx.x, nb2, nb1, p2, bi);
+    int x, y, z;
+    if (p2) {
+        const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m2);
+        if (linear_site_at<BLK>(m2, bi, x, y, z))
+            collide_mom_site_buf<ORDER, ST, PSI, NODE>(m2, db, mom, x, y, z);
+    } else {
+        const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m1);
+        if (linear_site_at<BLK>(m1, bi, x, y, z)) moments_site_buf<ST, NODE>(m1, sb, mom, x, y, z);
+    }
 }
 
 template <class ST>
@@ -546,35 +599,44 @@ static void mom_blocks(const Member &m, bool lds, dim3 *gm, dim3 *bm, dim3 *gc,
     }
 }
 
-// Slabs of at least the stencil's z-radius planes and about kSlabMomentBytes
-// of moments each, for lattices with more than kSlabMinMomentBytes of moments
-// (24 B per site in FP32); stochastic rounding keeps whole launches (its step
-// counter advances at the first block of pass 1).  Order, n slabs:
-// P1(n-1), P1(0), then P1(k+1), P2(k) for k = 0..n-2, then P2(n-1): pass 2 of
-// slab k needs the moments of slabs k-1..k+1, and pass 1 only reads the
-// source buffer, which no pass 2 writes.
-static constexpr size_t kSlabMomentBytes = (size_t)12 << 20;
-static constexpr size_t kSlabMinMomentBytes = (size_t)64 << 20;
+// Slabs for lattices with more than kSlabMinMomentBytes of moments (24 B per
+// site); below that the whole moment field stays in the 256 MB Infinity Cache
+// between the passes.  A slab has at least the stencil's z-radius planes and
+// about kSlabTouchBytes of traffic per pair of passes (moments written and
+// read, populations read and written: 352 B per site in FP32, 200 B in
+// FP16/BF16), so the slabs of the launches in flight stay cached.
+// Stochastic rounding keeps whole launches (its step counter advances at the
+// first block of pass 1).  Pass 2 of slab k needs the
+// moments of slabs k-1..k+1, and pass 1 only reads the source buffer, which no
+// pass 2 writes.  n slabs run in n + 2 launches:
+//   P1(n-1);  P1(0..1);  then for k = 0..n-1 one launch of P2(k) together
+//   with P1(k+2) while k+2 <= n-2 (k_slab_pair), P2(k) alone after that.
+// Pass 2 of slab k then finds slabs k-1..k+1 done, and the pass 1 beside it
+// writes slab k+2, which it does not read.
+static constexpr size_t kSlabTouchBytes = (size_t)192 << 20;
+static constexpr size_t kSlabMinMomentBytes = (size_t)128 << 20;
 
 std::vector<SlabOp> slab_schedule(const StepKey &k, const Member &m) {
     std::vector<SlabOp> ops;
     if (k.dim != 3 || k.storage == ST_F64 || k.mom != 1 || k.big || m.sr) return ops;
-    const size_t plane = (size_t)6 * 4 * m.nx * m.ny;
-    if (plane * m.nz <= kSlabMinMomentBytes) return ops;
+    const size_t sites = (size_t)m.nx * m.ny;
+    if (sites * 24 * m.nz <= kSlabMinMomentBytes) return ops;
+    const size_t pop = k.storage == ST_F32 ? 4 : 2;
+    const size_t touch = 2 * 24 + 4 * 19 * pop + (k.node ? 24 : 0);
     const int rz = k.order == 4 ? 1 : 2;
-    const int per = std::max(rz, (int)(kSlabMomentBytes / plane));
+    const int per = std::max(rz, (int)(kSlabTouchBytes / (sites * touch)));
     const int n = (m.nz + per - 1) / per;
     if (n < 3 || m.nz / n < rz) return ops;
     std::vector<int> z0(n + 1, 0);
     for (int i = 0; i < n; ++i) z0[i + 1] = z0[i] + m.nz / n + (i < m.nz % n ? 1 : 0);
-    auto op = [&](int pass, int i) { ops.push_back({pass, z0[i], z0[i + 1] - z0[i]}); };
-    op(1, n - 1);
-    op(1, 0);
-    for (int i = 0; i + 1 < n; ++i) {
-        if (i + 1 != n - 1) op(1, i + 1);
-        op(2, i);
+    ops.push_back({1, z0[n - 1], z0[n] - z0[n - 1]});
+    ops.push_back({1, z0[0], z0[2] - z0[0]});  // n >= 3: slabs 0 and 1
+    for (int i = 0; i < n; ++i) {
+        if (i + 2 <= n - 2)
+            ops.push_back({3, z0[i], z0[i + 1] - z0[i], z0[i + 2], z0[i + 3] - z0[i + 2]});
+        else
+            ops.push_back({2, z0[i], z0[i + 1] - z0[i]});
     }
-    op(2, n - 1);
     return ops;
 }
 
@@ -602,7 +664,16 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
                             ms.zoff = o.z0;
                             ms.znum = o.nz;
                             const dim3 g(linear_blocks(m, o.nz, SLAB_BLOCK));
-                            if (o.pass == 1)
+                            if (o.pass == 3) {
+                                Member m1 = m;
+                                m1.zoff = o.z1;
+                                m1.znum = o.n1;
+                                const int nb2 = (int)g.x;
+                                const int nb1 = linear_blocks(m, o.n1, SLAB_BLOCK);
+                                hipLaunchKernelGGL((k_slab_pair<O, ST, P, SLAB_BLOCK, NODE>),
+                                                   dim3(nb2 + nb1), b, 0, st, ms, m1, nb2, nb1,
+                                                   (const T *)src, (T *)dst, (R *)dens);
+                            } else if (o.pass == 1)
                                 hipLaunchKernelGGL((k_moments_buf<ST, SLAB_BLOCK, NODE>), g, b, 0,
                                                    st, ms, (const T *)src, (R *)dens);
                             else
@@ -697,10 +768,56 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dn, NodeLaunch *sn,
     return ok;
 }
 
+bool node_slab_pair(const StepKey &k, NodeLaunch *pn) {
+    bool ok = false;
+    dispatch_storage(k.storage, [&](auto stv) {
+        using ST = decltype(stv);
+        dispatch_shape<ST>(k, [&](auto Dc, auto Oc, auto Pc) {
+            constexpr int D = decltype(Dc)::value;
+            constexpr int O = decltype(Oc)::value;
+            constexpr int P = decltype(Pc)::value;
+            if constexpr (buf_form<D, ST>()) {
+                auto set = [&](auto Nc) {
+                    constexpr bool NODE = decltype(Nc)::value;
+                    pn->func = (void *)&k_slab_pair<O, ST, P, SLAB_BLOCK, NODE>;
+                    pn->block = dim3(SLAB_BLOCK, 1, 1);
+                    pn->shmem = 0;
+                    ok = true;
+                };
+                if (!k.node) {
+                    set(std::false_type{});
+                } else if constexpr (node_form<D, ST>()) {
+                    set(std::true_type{});
+                }
+            }
+        });
+    });
+    return ok;
+}
+
+int resident_blocks(const void *f, int threads, unsigned shmem) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, int, unsigned>, int> cache;
+    constexpr int kNoLimit = 1 << 30;  // occupancy unknown: keep the caller's grid
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return kNoLimit;
+    const auto key = std::make_tuple(f, dev, threads, shmem);
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, threads, shmem) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        per < 1 || ncu < 1)
+        return kNoLimit;
+    return cache[key] = per * ncu;
+}
+
 hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
                                  const Tile *d_tiles, int ntiles,
                                  const void *src, void *dst, void *dens,
-                                 int grid, hipStream_t st) {
+                                 int grid, hipStream_t st, int passes) {
+    const bool p1 = passes & 1, p2 = passes & 2;
     hipError_t err = hipErrorInvalidValue;
     dispatch_storage(k.storage, [&](auto stv) {
         using ST = decltype(stv);
@@ -714,30 +831,36 @@ hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
             bool done = false;
             if constexpr (buf_form<D, ST>()) {
                 if (k.mom && !k.big) {
-                    hipLaunchKernelGGL((kb_moments_buf<ST>), dim3(grid), b, 0, st,
-                                       d_members, d_tiles, ntiles, (const T *)src,
-                                       (R *)dens);
-                    hipLaunchKernelGGL((kb_collide_mom_buf<O, ST, P>), dim3(grid), b, 0,
-                                       st, d_members, d_tiles, ntiles, (const T *)src,
-                                       (T *)dst, (const R *)dens);
+                    if (p1)
+                        hipLaunchKernelGGL((kb_moments_buf<ST>), dim3(grid), b, 0, st,
+                                           d_members, d_tiles, ntiles, (const T *)src,
+                                           (R *)dens);
+                    if (p2)
+                        hipLaunchKernelGGL((kb_collide_mom_buf<O, ST, P>), dim3(grid), b, 0,
+                                           st, d_members, d_tiles, ntiles, (const T *)src,
+                                           (T *)dst, (const R *)dens);
                     done = true;
                 }
             }
             if (done) {
             } else if (k.mom) {
-                hipLaunchKernelGGL((kb_moments<D, ST>), dim3(grid), b, 0, st,
-                                   d_members, d_tiles, ntiles, (const T *)src,
-                                   (R *)dens);
-                hipLaunchKernelGGL((kb_collide_mom<D, O, ST, P>), dim3(grid), b, 0,
-                                   st, d_members, d_tiles, ntiles, (const T *)src,
-                                   (T *)dst, (const R *)dens);
+                if (p1)
+                    hipLaunchKernelGGL((kb_moments<D, ST>), dim3(grid), b, 0, st,
+                                       d_members, d_tiles, ntiles, (const T *)src,
+                                       (R *)dens);
+                if (p2)
+                    hipLaunchKernelGGL((kb_collide_mom<D, O, ST, P>), dim3(grid), b, 0,
+                                       st, d_members, d_tiles, ntiles, (const T *)src,
+                                       (T *)dst, (const R *)dens);
             } else {
-                hipLaunchKernelGGL((kb_density<D, ST>), dim3(grid), b, 0, st,
-                                   d_members, d_tiles, ntiles, (const T *)src,
-                                   (R *)dens);
-                hipLaunchKernelGGL((kb_collide<D, O, ST, P>), dim3(grid), b, 0,
-                                   st, d_members, d_tiles, ntiles, (const T *)src,
-                                   (T *)dst, (const R *)dens);
+                if (p1)
+                    hipLaunchKernelGGL((kb_density<D, ST>), dim3(grid), b, 0, st,
+                                       d_members, d_tiles, ntiles, (const T *)src,
+                                       (R *)dens);
+                if (p2)
+                    hipLaunchKernelGGL((kb_collide<D, O, ST, P>), dim3(grid), b, 0,
+                                       st, d_members, d_tiles, ntiles, (const T *)src,
+                                       (T *)dst, (const R *)dens);
             }
             err = hipGetLastError();
         });

@@ -133,7 +133,7 @@ def test_node_storage_slab_schedule_single_step():
     stored exactly; interface nodes carry the rounding of the initial and the
     new offsets (the oracle starts from the exact densities, the GPU from
     their encoding)."""
-    nz, ny, nx, R0 = 96, 192, 192, 30.0
+    nz, ny, nx, R0 = 160, 192, 192, 30.0
     nA, nB = inputs.droplet(nx, ny, nz, R=R0, a_rich=False, bulk=inputs.FLAT_GUESS[-0.2])
     sim = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (nz, ny, nx), g=G_ASYM,
                                 storage=scmc.F16_NODE))
