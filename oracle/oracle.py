@@ -67,6 +67,7 @@ def lib():
         L.orc_bulk_pressure.argtypes = [pp, ctypes.c_double, ctypes.c_double]
         L.orc_bulk_pressure.restype = ctypes.c_double
         L.orc_droplet_observables.argtypes = [pp, dp, ctypes.c_double, dp, dp, dp]
+        L.orc_shell_observables.argtypes = [pp, dp, ctypes.c_double, dp, dp, dp]
         L.orc_flat_sigma0.argtypes = [pp, dp, dp, dp]
         L.orc_flat_sigma0.restype = ctypes.c_double
         L.orc_stats.argtypes = [pp, dp, dp]
@@ -212,6 +213,27 @@ class Oracle:
             raise RuntimeError("orc_droplet_observables failed")
         keys = ["P_in", "P_out", "dP", "C_d", "R_s", "R_s_grid", "sigma_s",
                 "sigma_grid_min", "max_PyyPzz"]
+        d = dict(zip(keys, obs.tolist()))
+        d["PN"] = PN
+        d["PT"] = PT
+        return d
+
+    def shell_observables(self, R0):
+        """The droplet analysis on shell-averaged profiles: PN[k], PT[k] are
+        the means of the normal and tangential pressure over the shells
+        k = floor(|x - c| + 1/2), k = 0..min(extent) // 2 (a variant of the
+        axis line, not the paper's definition)."""
+        dims = self.shape if self.dim == 3 else self.shape[-2:]
+        rmax = min(dims) // 2
+        obs = np.zeros(9)
+        PN = np.zeros(rmax + 1)
+        PT = np.zeros(rmax + 1)
+        rc = lib().orc_shell_observables(ctypes.byref(self.p), _dp(self.f), float(R0),
+                                         _dp(obs), _dp(PN), _dp(PT))
+        if rc != 0:
+            raise RuntimeError("orc_shell_observables failed")
+        keys = ["P_in", "P_out", "dP", "C_d", "R_s", "R_s_grid", "sigma_s",
+                "sigma_grid_min"]
         d = dict(zip(keys, obs.tolist()))
         d["PN"] = PN
         d["PT"] = PT

@@ -711,58 +711,33 @@ double orc_bulk_pressure(const orc_problem *p, double nA, double nB)
            0.5 * p->g[0][0] * psA * psA + 0.5 * p->g[1][1] * psB * psB;
 }
 
-/* Droplet analysis (Sec. 3, eq. gen_sigma, and Sec. 4).
+/* Droplet analysis (Sec. 3, eq. gen_sigma, and Sec. 4) from a nodal
+ * profile PTr[r], r = 0..rmax, of the tangential pressure.
  * With P_J(r;R) = P_in - dP theta(r - R), the Heaviside part of
  * sigma[R] = int_0^inf (r/R)^(d-1) [P_J(r;R) - P_T(r)] dr integrates exactly,
  * leaving sigma[R] = C_d / R^(d-1) + dP R / d with
  * C_d = int_0^inf r^(d-1) (P_out - P_T(r)) dr, where P_T between lattice
- * nodes is the linear interpolant of its nodal values on the x axis.
+ * nodes is the linear interpolant of its nodal values.
  * Its minimum is R_s = (d (d-1) C_d / dP)^(1/d), where the Laplace law
  * dP = (d-1) sigma_s / R_s holds.  The grid scan locates the same minimum
- * numerically as an independent check of that algebra. */
-int orc_droplet_observables(const orc_problem *p, const double *f, double R0,
-                            double *obs, double *PN, double *PT)
+ * numerically as an independent check of that algebra.  obs[0..7] as
+ * orc_droplet_observables. */
+static void sigma_from_profile(int d, double Pin, double Pout, const double *PTr,
+                               int rmax, double R0, double *obs)
 {
-    int d = p->dim, r, rmax, k;
-    long N = nsites(p);
-    int cx = p->nx / 2, cy = p->ny / 2, cz = p->nz / 2;
-    double *n = (double *)malloc(sizeof(double) * 2 * N);
-    double Pin, Pout, dP, Cd = 0.0, Rs, best = 1e300, Rbest = 0.0;
-    double maxdiff = 0.0, *gline;
-    long sc, so;
-    int nR, kbest = -1;
+    double dP = Pin - Pout, Cd = 0.0, Rs, best = 1e300, Rbest;
+    int r, k, nR, kbest = -1;
     double *sig;
-    if (!n) return -1;
-    if (d == 2) cz = 0;
-    orc_density(p, f, n);
-    sc = site_of(p, cx, cy, cz);
-    so = site_of(p, (cx + p->nx / 2) % p->nx, (cy + p->ny / 2) % p->ny,
-                 d == 3 ? (cz + p->nz / 2) % p->nz : 0);
-    Pin = orc_bulk_pressure(p, n[sc], n[N + sc]);
-    Pout = orc_bulk_pressure(p, n[so], n[N + so]);
-    dP = Pin - Pout;
-    rmax = p->nx / 2;
-    gline = (double *)malloc(sizeof(double) * (rmax + 1));
-    for (r = 0; r <= rmax; r++) {
-        double P6[6];
-        long s = site_of(p, (cx + r) % p->nx, cy, cz);
-        orc_pressure_tensor_site(p, n, s, P6);
-        if (PN) PN[r] = P6[0];
-        if (PT) PT[r] = P6[1];
-        if (d == 3 && fabs(P6[1] - P6[2]) > maxdiff)
-            maxdiff = fabs(P6[1] - P6[2]);
-        gline[r] = Pout - P6[1];
-    }
     /* C_d = int_0^rmax r^(d-1) g(r) dr with g the piecewise-linear
      * interpolant of P_out - P_T between the lattice nodes, integrated
      * exactly on every interval [k, k+1] */
     for (r = 0; r < rmax; r++) {
         double a = r, b = r + 1.0, m = d - 1;
+        double g0 = Pout - PTr[r], g1 = Pout - PTr[r + 1];
         double I0 = (pow(b, m + 1) - pow(a, m + 1)) / (m + 1);
         double I1 = (pow(b, m + 2) - pow(a, m + 2)) / (m + 2) - a * I0;
-        Cd += gline[r] * I0 + (gline[r + 1] - gline[r]) * I1;
+        Cd += g0 * I0 + (g1 - g0) * I1;
     }
-    free(gline);
     Rs = pow(d * (d - 1) * Cd / dP, 1.0 / d);
     /* grid scan of sigma[R] on [R0/2, 2 R0] in steps of 0.01 */
     nR = (int)floor((2.0 * R0 - 0.5 * R0) / 0.01) + 1;
@@ -782,6 +757,7 @@ int orc_droplet_observables(const orc_problem *p, const double *f, double R0,
         double den = ym - 2.0 * y0 + yp;
         if (den != 0.0) Rbest += 0.01 * 0.5 * (ym - yp) / den;
     }
+    free(sig);
     obs[0] = Pin;
     obs[1] = Pout;
     obs[2] = dP;
@@ -790,8 +766,122 @@ int orc_droplet_observables(const orc_problem *p, const double *f, double R0,
     obs[5] = Rbest;
     obs[6] = dP * Rs / (d - 1);
     obs[7] = best;
+}
+
+/* The probes of the droplet analysis: bulk pressure (eq. bulkp) at the centre
+ * node c = floor(L/2) and at (c + floor(L/2)) mod L. */
+static void pressure_probes(const orc_problem *p, const double *n, double *Pin,
+                            double *Pout)
+{
+    long N = nsites(p);
+    int d = p->dim, cx = p->nx / 2, cy = p->ny / 2, cz = d == 3 ? p->nz / 2 : 0;
+    long sc = site_of(p, cx, cy, cz);
+    long so = site_of(p, (cx + p->nx / 2) % p->nx, (cy + p->ny / 2) % p->ny,
+                      d == 3 ? (cz + p->nz / 2) % p->nz : 0);
+    *Pin = orc_bulk_pressure(p, n[sc], n[N + sc]);
+    *Pout = orc_bulk_pressure(p, n[so], n[N + so]);
+}
+
+/* The axis line (Sec. 3): P_N = P^xx and P_T = P^yy at the nodes
+ * r = 0..nx/2 along +x from the centre node; obs[8] = max |P^yy - P^zz| on
+ * the line (3D). */
+int orc_droplet_observables(const orc_problem *p, const double *f, double R0,
+                            double *obs, double *PN, double *PT)
+{
+    int d = p->dim, r, rmax;
+    long N = nsites(p);
+    int cx = p->nx / 2, cy = p->ny / 2, cz = d == 3 ? p->nz / 2 : 0;
+    double *n = (double *)malloc(sizeof(double) * 2 * N);
+    double Pin, Pout, maxdiff = 0.0, *pt;
+    if (!n) return -1;
+    orc_density(p, f, n);
+    pressure_probes(p, n, &Pin, &Pout);
+    rmax = p->nx / 2;
+    pt = (double *)malloc(sizeof(double) * (rmax + 1));
+    for (r = 0; r <= rmax; r++) {
+        double P6[6];
+        long s = site_of(p, (cx + r) % p->nx, cy, cz);
+        orc_pressure_tensor_site(p, n, s, P6);
+        if (PN) PN[r] = P6[0];
+        if (PT) PT[r] = P6[1];
+        if (d == 3 && fabs(P6[1] - P6[2]) > maxdiff)
+            maxdiff = fabs(P6[1] - P6[2]);
+        pt[r] = P6[1];
+    }
+    sigma_from_profile(d, Pin, Pout, pt, rmax, R0, obs);
     obs[8] = maxdiff;
-    free(sig);
+    free(pt);
+    free(n);
+    return 0;
+}
+
+/* Shell-averaged pressure profiles (a variant of the axis line, not the
+ * paper's definition).  Every node x at distance r = |x - c| from the centre
+ * node c (no periodic image: x - c in [-floor(L/2), L - 1 - floor(L/2)])
+ * belongs to shell k = floor(r + 1/2).  There, with the unit vector
+ * u = (x - c) / r, the normal and tangential pressures are
+ *   P_N = u . P . u,   P_T = (tr P - P_N) / (d - 1),
+ * and P_N = P_T = tr P / d at the centre node.  PN[k], PT[k] are their means
+ * over shell k for k = 0..rmax, rmax = floor(min extent / 2) (the largest
+ * shell that every axis still reaches), and the droplet analysis runs on PT
+ * as on the axis line.  obs[8] = the largest standard deviation of P_T within
+ * a shell. */
+int orc_shell_observables(const orc_problem *p, const double *f, double R0,
+                          double *obs, double *PN, double *PT)
+{
+    int d = p->dim, x, y, z, k, rmax;
+    long N = nsites(p);
+    int cx = p->nx / 2, cy = p->ny / 2, cz = d == 3 ? p->nz / 2 : 0;
+    int nz = d == 3 ? p->nz : 1;
+    double *n = (double *)malloc(sizeof(double) * 2 * N);
+    double *sn, *st, *cnt, *pt, Pin, Pout;
+    if (!n) return -1;
+    rmax = p->nx < p->ny ? p->nx : p->ny;
+    if (d == 3 && p->nz < rmax) rmax = p->nz;
+    rmax /= 2;
+    sn = (double *)calloc(rmax + 1, sizeof(double));
+    st = (double *)calloc(rmax + 1, sizeof(double));
+    cnt = (double *)calloc(rmax + 1, sizeof(double));
+    pt = (double *)malloc(sizeof(double) * (rmax + 1));
+    orc_density(p, f, n);
+    pressure_probes(p, n, &Pin, &Pout);
+    for (z = 0; z < nz; z++)
+        for (y = 0; y < p->ny; y++)
+            for (x = 0; x < p->nx; x++) {
+                double P6[6], v[3], r2, r, tr, pn, ptv;
+                v[0] = x - cx;
+                v[1] = y - cy;
+                v[2] = d == 3 ? z - cz : 0.0;
+                r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+                r = sqrt(r2);
+                k = (int)floor(r + 0.5);
+                if (k > rmax) continue;
+                orc_pressure_tensor_site(p, n, site_of(p, x, y, z), P6);
+                tr = P6[0] + P6[1] + (d == 3 ? P6[2] : 0.0);
+                if (r2 == 0.0) {
+                    pn = tr / d;
+                } else {
+                    /* u . P . u with P symmetric: P6 = xx, yy, zz, xy, xz, yz */
+                    pn = (v[0] * v[0] * P6[0] + v[1] * v[1] * P6[1] +
+                          v[2] * v[2] * P6[2] + 2.0 * v[0] * v[1] * P6[3] +
+                          2.0 * v[0] * v[2] * P6[4] + 2.0 * v[1] * v[2] * P6[5]) / r2;
+                }
+                ptv = (tr - pn) / (d - 1);
+                sn[k] += pn;
+                st[k] += ptv;
+                cnt[k] += 1.0;
+            }
+    for (k = 0; k <= rmax; k++) {
+        pt[k] = st[k] / cnt[k];
+        if (PN) PN[k] = sn[k] / cnt[k];
+        if (PT) PT[k] = pt[k];
+    }
+    sigma_from_profile(d, Pin, Pout, pt, rmax, R0, obs);
+    obs[8] = 0.0;
+    free(sn);
+    free(st);
+    free(cnt);
+    free(pt);
     free(n);
     return 0;
 }

@@ -90,6 +90,12 @@ double orc_bulk_pressure(const orc_problem *p, double nA, double nB);
 int orc_droplet_observables(const orc_problem *p, const double *f, double R0,
                             double *obs, double *PN, double *PT);
 
+/* Shell-averaged variant: PN, PT (nullable, floor(min extent / 2) + 1
+ * values) are the means of u.P.u and (tr P - u.P.u)/(d-1) over the shells
+ * k = floor(|x - c| + 1/2); obs as orc_droplet_observables, obs[8] = 0. */
+int orc_shell_observables(const orc_problem *p, const double *f, double R0,
+                          double *obs, double *PN, double *PT);
+
 /* Flat-interface profiles: PN[x], PT[x] = P^xx, P^yy averaged over y (and z);
  * returns sigma0 = sum_{x = nx/2}^{nx-1} (PN - PT). */
 double orc_flat_sigma0(const orc_problem *p, const double *f, double *PN,
