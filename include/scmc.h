@@ -127,7 +127,7 @@ typedef enum {
                                  hash of (seed, step, site, J, i), so runs
                                  are reproducible.  Two-pass designs only. */
 } scmc_rounding;
-typedef enum { SCMC_OBS_FLAT = 0, SCMC_OBS_DROPLET = 1 } scmc_obs_kind;
+typedef enum { SCMC_OBS_FLAT = 0, SCMC_OBS_DROPLET = 1, SCMC_OBS_SHELL = 2 } scmc_obs_kind;
 
 typedef struct {
     int lattice;      /* scmc_lattice */
@@ -174,7 +174,8 @@ typedef struct {
                             [R0/2, 2 R0], step 0.01 (cross-check) */
     double sigma0;       /* flat: sum_{x = nx/2}^{nx-1} (P^xx - P^yy), both
                             averaged over y, z */
-    double max_PyyPzz;   /* max |P^yy - P^zz| on the droplet line (3D) */
+    double max_PyyPzz;   /* max |P^yy - P^zz| on the droplet line (3D);
+                            0 for kind SHELL */
     int64_t step;
 } scmc_obs;
 
@@ -251,7 +252,17 @@ int scmc_stats_get(scmc_sim *s, scmc_stats *out);
 /* Observables of the current state; PN, PT (nullable) receive P^xx, P^yy on
  * the droplet line r = 0..floor(nx/2) (kind DROPLET, nx/2 + 1 values) or the
  * transverse-averaged profiles (kind FLAT, nx values).  R0 sets the grid of
- * the sigma[R] scan (DROPLET). */
+ * the sigma[R] scan (DROPLET, SHELL).
+ * Kind SHELL is a variant of the droplet analysis that is not the paper's
+ * definition (Sec. 3 uses the axis line): every node x at distance
+ * r = |x - c| from the centre node c = floor(L/2) (no periodic image) belongs
+ * to shell k = floor(r + 1/2), k = 0..rmax with rmax = floor(min extent / 2);
+ * with u = (x - c) / r it carries P_N = u.P.u and P_T = (tr P - P_N)/(d - 1)
+ * of the lattice tensor (eq. sm:pt; tr P / d at the centre).  PN, PT receive
+ * the shell means (rmax + 1 values) and P_in, P_out, dP, C_d, R_s, sigma_s,
+ * R_s_grid follow from the shell P_T as from the line's; max_PyyPzz = 0.
+ * Averaging over whole shells cuts the lattice and rounding noise of R_s.
+ * The sums run in a fixed order (bitwise reproducible). */
 int scmc_observables(scmc_sim *s, int kind, double R0, scmc_obs *out,
                      double *PN, double *PT);
 

@@ -8,6 +8,8 @@
 // same state give bitwise-identical results.
 #include "site_ops.h"
 
+#include <algorithm>
+
 namespace scmc {
 
 // Common velocity in FP64 from the components' momenta jm[J] = sum_i f_i xi_i:
@@ -267,6 +269,37 @@ __device__ void ptensor_diag(const Member &m, const double *__restrict__ dens,
     for (int k = 0; k < 3; ++k) P[k] = ideal + 0.5 * acc[k];
 }
 
+// The full tensor at one site: xx, yy, zz, xy, xz, yz (the diagonal as
+// ptensor_diag).
+template <int D, int ORDER, int PSI>
+__device__ void ptensor_full(const Member &m, const double *__restrict__ dens,
+                             int x, int y, int z, double (&P)[6]) {
+    using S = Stencil<D, ORDER>;
+    const long s = ((long)z * m.ny + y) * m.nx + x;
+    const double nA = dens[s], nB = dens[m.N + s];
+    const double pA = psi_of<double, PSI>(nA), pB = psi_of<double, PSI>(nB);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < S::NE; ++a) {
+        constexpr auto T = S::T;
+        const int e3[3] = {T.e[a][0], T.e[a][1], T.e[a][2]};
+        const int xs = wrap1(x + e3[0], m.nx);
+        const int ys = wrap1(y + e3[1], m.ny);
+        const int zs = D == 3 ? wrap1(z + e3[2], m.nz) : 0;
+        const long t = ((long)zs * m.ny + ys) * m.nx + xs;
+        const double nAt = dens[t], nBt = dens[m.N + t];
+        const double inter =
+            m.g[0][1] * nA * nBt + m.g[1][0] * nB * nAt +
+            m.g[0][0] * pA * psi_of<double, PSI>(nAt) +
+            m.g[1][1] * pB * psi_of<double, PSI>(nBt);
+        constexpr int MU[6] = {0, 1, 2, 0, 0, 1}, NU[6] = {0, 1, 2, 1, 2, 2};
+        for (int k = 0; k < 6; ++k)
+            acc[k] += T.W[a] * (double)(e3[MU[k]] * e3[NU[k]]) * inter;
+    }
+    const double ideal = (nA + nB) / 3.0;
+    for (int k = 0; k < 6; ++k) P[k] = (k < 3 ? ideal : 0.0) + 0.5 * acc[k];
+}
+
 // Bulk pressure (eq. bulkp, e2 = 1) of the concentrations at one site.
 template <int PSI>
 __device__ double bulk_pressure(const Member &m, double nA, double nB) {
@@ -318,6 +351,122 @@ __global__ void __launch_bounds__(LINE_THREADS)
         out[3 * (rmax + 1) + 1] = Pout;
         out[3 * (rmax + 1) + 2] = v[0];
     }
+}
+
+// Shell-averaged profiles (a variant of the axis line): the node x at
+// distance r = |x - c| from the centre node c = floor(L/2) (no periodic
+// image) is in shell k = floor(r + 1/2); with u = (x - c) / r it carries
+// P_N = u.P.u and P_T = (tr P - P_N) / (d - 1) (tr P / d at the centre).
+// Block b sums the nodes [b per, (b + 1) per) of shells 0..rmax in a fixed
+// order: the block stages 256 nodes in LDS, then the thread that owns shell
+// k (k mod 256, up to SH_MAXQ shells each) adds the staged nodes of shell k
+// one by one, so every sum has the same order on every run.
+constexpr int SH_THREADS = 256, SH_MAXQ = 4;
+template <int D, int ORDER, int PSI>
+__global__ void __launch_bounds__(SH_THREADS)
+    k_shell(Member m, int rmax, long per, const double *__restrict__ dens,
+            double *__restrict__ partials) {
+    __shared__ int key[SH_THREADS];
+    __shared__ double vn[SH_THREADS], vt[SH_THREADS];
+    const int tid = threadIdx.x, nshell = rmax + 1;
+    const int nxy = m.nx * m.ny;
+    const int cx = m.nx / 2, cy = m.ny / 2, cz = D == 3 ? m.nz / 2 : 0;
+    double aN[SH_MAXQ], aT[SH_MAXQ], aC[SH_MAXQ];
+#pragma unroll
+    for (int q = 0; q < SH_MAXQ; ++q) aN[q] = aT[q] = aC[q] = 0;
+    const long s0 = (long)blockIdx.x * per, s1 = min((long)m.N, s0 + per);
+    for (long base = s0; base < s1; base += SH_THREADS) {
+        const long s = base + tid;
+        int k = -1;
+        double pn = 0, pt = 0;
+        if (s < s1) {
+            const int z = (int)(s / nxy), rr = (int)(s - (long)z * nxy);
+            const int y = rr / m.nx, x = rr - y * m.nx;
+            const double v[3] = {(double)(x - cx), (double)(y - cy), (double)(z - cz)};
+            const double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+            k = (int)floor(sqrt(r2) + 0.5);
+            if (k <= rmax) {
+                double P[6];
+                ptensor_full<D, ORDER, PSI>(m, dens, x, y, z, P);
+                const double tr = P[0] + P[1] + (D == 3 ? P[2] : 0.0);
+                pn = r2 == 0 ? tr / D
+                             : (v[0] * v[0] * P[0] + v[1] * v[1] * P[1] + v[2] * v[2] * P[2] +
+                                2.0 * v[0] * v[1] * P[3] + 2.0 * v[0] * v[2] * P[4] +
+                                2.0 * v[1] * v[2] * P[5]) / r2;
+                pt = (tr - pn) / (D - 1);
+            } else {
+                k = -1;
+            }
+        }
+        key[tid] = k;
+        vn[tid] = pn;
+        vt[tid] = pt;
+        __syncthreads();
+        for (int j = 0; j < SH_THREADS; ++j) {
+            const int kj = key[j];
+#pragma unroll
+            for (int q = 0; q < SH_MAXQ; ++q)
+                if (kj == tid + q * SH_THREADS) {
+                    aN[q] += vn[j];
+                    aT[q] += vt[j];
+                    aC[q] += 1.0;
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < SH_MAXQ; ++q) {
+        const int k = tid + q * SH_THREADS;
+        if (k < nshell) {
+            double *o = partials + ((long)blockIdx.x * nshell + k) * 3;
+            o[0] = aN[q];
+            o[1] = aT[q];
+            o[2] = aC[q];
+        }
+    }
+}
+
+// Shell means over the blocks in order, the two pressure probes and
+// C_d = int r^(d-1) (P_out - P_T) dr on the shell profile (P_T linear
+// between shells, each cell integrated exactly, summed in order of r):
+// out[k], out[nshell + k] = P_N, P_T of shell k; out[2 nshell ..] = P_in,
+// P_out, C_d.
+template <int D, int PSI>
+__global__ void __launch_bounds__(SH_THREADS)
+    k_shell_final(Member m, int rmax, int nb, const double *__restrict__ dens,
+                  const double *__restrict__ partials, double *__restrict__ out) {
+    const int tid = threadIdx.x, nshell = rmax + 1;
+    for (int k = tid; k < nshell; k += SH_THREADS) {
+        double sn = 0, st = 0, sc = 0;
+        for (int b = 0; b < nb; ++b) {
+            const double *p = partials + ((long)b * nshell + k) * 3;
+            sn += p[0];
+            st += p[1];
+            sc += p[2];
+        }
+        out[k] = sn / sc;
+        out[nshell + k] = st / sc;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    const int cx = m.nx / 2, cy = m.ny / 2, cz = D == 3 ? m.nz / 2 : 0;
+    const long sc = ((long)cz * m.ny + cy) * m.nx + cx;
+    const int ox = (cx + m.nx / 2) % m.nx, oy = (cy + m.ny / 2) % m.ny;
+    const int oz = D == 3 ? (cz + m.nz / 2) % m.nz : 0;
+    const long so = ((long)oz * m.ny + oy) * m.nx + ox;
+    const double Pout = bulk_pressure<PSI>(m, dens[so], dens[m.N + so]);
+    double Cd = 0;
+    const double mexp = D - 1;
+    for (int r = 0; r < rmax; ++r) {
+        const double g0 = Pout - out[nshell + r], g1 = Pout - out[nshell + r + 1];
+        const double a = r, b = r + 1.0;
+        const double I0 = (pow(b, mexp + 1) - pow(a, mexp + 1)) / (mexp + 1);
+        const double I1 = (pow(b, mexp + 2) - pow(a, mexp + 2)) / (mexp + 2) - a * I0;
+        Cd += g0 * I0 + (g1 - g0) * I1;
+    }
+    out[2 * nshell] = bulk_pressure<PSI>(m, dens[sc], dens[m.N + sc]);
+    out[2 * nshell + 1] = Pout;
+    out[2 * nshell + 2] = Cd;
 }
 
 // One block per x: transverse averages of P^xx and P^yy.
@@ -508,6 +657,36 @@ hipError_t launch_line(const StepKey &k, const Member &m, const double *dens64,
         constexpr int P = decltype(Pc)::value;
         hipLaunchKernelGGL((k_line<D, O, P>), dim3(1), dim3(LINE_THREADS), 0,
                            st, m, dens64, out);
+        err = hipGetLastError();
+    });
+    return err;
+}
+
+int shell_rmax(const Member &m, int dim) {
+    int e = std::min(m.nx, m.ny);
+    if (dim == 3) e = std::min(e, m.nz);
+    return e / 2;
+}
+
+hipError_t launch_shell(const StepKey &k, const Member &m, const double *dens64,
+                        double *partials, long partial_capacity, double *out,
+                        hipStream_t st) {
+    const int rmax = shell_rmax(m, k.dim), nshell = rmax + 1;
+    if (nshell > SH_THREADS * SH_MAXQ) return hipErrorInvalidValue;
+    // blocks: at most 1024, as many as the partials hold (3 values per shell)
+    long nb = std::min(1024L, partial_capacity / (3L * nshell));
+    if (nb < 1) return hipErrorInvalidValue;
+    const long per = ((m.N + nb - 1) / nb + SH_THREADS - 1) / SH_THREADS * SH_THREADS;
+    nb = (m.N + per - 1) / per;
+    hipError_t err = hipErrorInvalidValue;
+    dispatch_all(k, [&](auto, auto Dc, auto Oc, auto Pc) {
+        constexpr int D = decltype(Dc)::value;
+        constexpr int O = decltype(Oc)::value;
+        constexpr int P = decltype(Pc)::value;
+        hipLaunchKernelGGL((k_shell<D, O, P>), dim3((unsigned)nb), dim3(SH_THREADS), 0, st, m,
+                           rmax, per, dens64, partials);
+        hipLaunchKernelGGL((k_shell_final<D, P>), dim3(1), dim3(SH_THREADS), 0, st, m, rmax,
+                           (int)nb, dens64, partials, out);
         err = hipGetLastError();
     });
     return err;

@@ -752,10 +752,37 @@ int fields_impl(Common &c, const Lat &L, const void *pop_base, double *nA,
     return SCMC_OK;
 }
 
+// sigma[R] = C_d / R^(d-1) + dP R / d (the Heaviside part of eq. gen_sigma
+// integrated exactly) from the probes and C_d of a P_T profile; minimum at
+// R_s = (d (d-1) C_d / dP)^(1/d), and the grid scan on [R0/2, 2 R0].
+void droplet_sigma(int d, double Pin, double Pout, double Cd, double R0, scmc_obs *out) {
+    const double dP = Pin - Pout;
+    out->P_in = Pin;
+    out->P_out = Pout;
+    out->dP = dP;
+    out->C_d = Cd;
+    out->R_s = std::pow(d * (d - 1) * Cd / dP, 1.0 / d);
+    out->sigma_s = dP * out->R_s / (d - 1);
+    const int nR = (int)std::floor((2.0 * R0 - 0.5 * R0) / 0.01) + 1;
+    std::vector<double> sg(nR);
+    int kb = 0;
+    for (int k = 0; k < nR; ++k) {
+        const double R = 0.5 * R0 + 0.01 * k;
+        sg[k] = Cd / std::pow(R, d - 1) + dP * R / d;
+        if (sg[k] < sg[kb]) kb = k;
+    }
+    double Rg = 0.5 * R0 + 0.01 * kb;
+    if (kb > 0 && kb < nR - 1) {
+        const double den = sg[kb - 1] - 2 * sg[kb] + sg[kb + 1];
+        if (den != 0) Rg += 0.01 * 0.5 * (sg[kb - 1] - sg[kb + 1]) / den;
+    }
+    out->R_s_grid = Rg;
+}
+
 int obs_impl(Common &c, const Lat &L, const void *pop_base, int kind, double R0,
              scmc_obs *out, double *PN, double *PT, int64_t step) {
     if (!out) return fail(c, SCMC_EINVAL, "out is NULL");
-    if (kind != SCMC_OBS_FLAT && kind != SCMC_OBS_DROPLET)
+    if (kind != SCMC_OBS_FLAT && kind != SCMC_OBS_DROPLET && kind != SCMC_OBS_SHELL)
         return fail(c, SCMC_EINVAL, "unknown observable kind %d", kind);
     const Member m = obs_member(c, L, pop_base);
     const int d = L.dim;
@@ -777,36 +804,26 @@ int obs_impl(Common &c, const Lat &L, const void *pop_base, int kind, double R0,
     }
     if (!(R0 > 0) || !std::isfinite(R0))
         return fail(c, SCMC_EINVAL, "R0 must be positive");
+    if (kind == SCMC_OBS_SHELL) {
+        const int nl = shell_rmax(m, d) + 1;
+        std::vector<double> h(2 * nl + 3);
+        HIPCHK(c, launch_shell(c.key, m, c.dens64, c.partials, (long)c.nblocks * 9, c.small,
+                               c.stream));
+        HIPCHK(c, hipMemcpyAsync(h.data(), c.small, h.size() * 8, hipMemcpyDeviceToHost,
+                                 c.stream));
+        HIPCHK(c, hipStreamSynchronize(c.stream));
+        droplet_sigma(d, h[2 * nl], h[2 * nl + 1], h[2 * nl + 2], R0, out);
+        if (PN) std::memcpy(PN, h.data(), nl * 8);
+        if (PT) std::memcpy(PT, h.data() + nl, nl * 8);
+        return SCMC_OK;
+    }
     const int rmax = m.nx / 2, nl = rmax + 1;
     std::vector<double> h(3 * nl + 3);
     HIPCHK(c, launch_line(c.key, m, c.dens64, c.small, c.stream));
     HIPCHK(c, hipMemcpyAsync(h.data(), c.small, h.size() * 8,
                              hipMemcpyDeviceToHost, c.stream));
     HIPCHK(c, hipStreamSynchronize(c.stream));
-    const double Pin = h[3 * nl], Pout = h[3 * nl + 1], Cd = h[3 * nl + 2];
-    const double dP = Pin - Pout;
-    out->P_in = Pin;
-    out->P_out = Pout;
-    out->dP = dP;
-    out->C_d = Cd;
-    // sigma[R] = C_d / R^(d-1) + dP R / d  (Heaviside part of eq. gen_sigma
-    // integrated exactly); minimum at R_s = (d (d-1) C_d / dP)^(1/d)
-    out->R_s = std::pow(d * (d - 1) * Cd / dP, 1.0 / d);
-    out->sigma_s = dP * out->R_s / (d - 1);
-    const int nR = (int)std::floor((2.0 * R0 - 0.5 * R0) / 0.01) + 1;
-    std::vector<double> sg(nR);
-    int kb = 0;
-    for (int k = 0; k < nR; ++k) {
-        const double R = 0.5 * R0 + 0.01 * k;
-        sg[k] = Cd / std::pow(R, d - 1) + dP * R / d;
-        if (sg[k] < sg[kb]) kb = k;
-    }
-    double Rg = 0.5 * R0 + 0.01 * kb;
-    if (kb > 0 && kb < nR - 1) {
-        const double den = sg[kb - 1] - 2 * sg[kb] + sg[kb + 1];
-        if (den != 0) Rg += 0.01 * 0.5 * (sg[kb - 1] - sg[kb + 1]) / den;
-    }
-    out->R_s_grid = Rg;
+    droplet_sigma(d, h[3 * nl], h[3 * nl + 1], h[3 * nl + 2], R0, out);
     double mx = 0;
     for (int r = 0; r < nl; ++r)
         if (d == 3) mx = std::max(mx, std::fabs(h[nl + r] - h[2 * nl + r]));

@@ -148,6 +148,14 @@ hipError_t launch_line(const StepKey &k, const Member &m, const double *dens64,
 hipError_t launch_monitor(const Member &m, int dim, const double *dens64, const double *u,
                           const double *u0, int rich, double n_out, double *partials,
                           double *out, hipStream_t st);
+// shell-averaged profiles (variant of the droplet line): shells k = 0..rmax,
+// rmax = shell_rmax = floor(min extent / 2); out[k], out[nshell + k] = P_N,
+// P_T; out[2 nshell ..] = P_in, P_out, C_d.  partials: capacity in doubles
+// (3 per shell and block)
+int shell_rmax(const Member &m, int dim);
+hipError_t launch_shell(const StepKey &k, const Member &m, const double *dens64,
+                        double *partials, long partial_capacity, double *out,
+                        hipStream_t st);
 // flat: out[0..nx) = <P^xx>_yz, out[nx..2nx) = <P^yy>_yz, out[2nx] = sigma0
 hipError_t launch_flat(const StepKey &k, const Member &m, const double *dens64,
                        double *out, hipStream_t st);

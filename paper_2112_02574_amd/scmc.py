@@ -23,7 +23,7 @@ F64, F32, F16_OFF, BF16_OFF, F16_NODE, BF16_NODE = 0, 1, 2, 3, 4, 5
 KERNEL_AUTO, KERNEL_TWO_PASS, KERNEL_FUSED, KERNEL_FUSED_REPULL, KERNEL_FUSED_PIPE = 0, 1, 2, 3, 4
 KERNEL_FUSED_MOM, KERNEL_FUSED_MOM_PIPE, KERNEL_TWO_PASS_MOM = 5, 6, 7
 ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
-OBS_FLAT, OBS_DROPLET = 0, 1
+OBS_FLAT, OBS_DROPLET, OBS_SHELL = 0, 1, 2
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16_OFF: "f16", BF16_OFF: "bf16", F16_NODE: "f16_node",
                  BF16_NODE: "bf16_node"}
 
@@ -161,6 +161,16 @@ def lib():
 
 def exported_symbols():
     return sorted(_SYMBOLS)
+
+
+def _profile_len(p, kind):
+    """Values of the PN / PT profiles of an observable kind."""
+    if kind == OBS_DROPLET:
+        return p.nx // 2 + 1
+    if kind == OBS_SHELL:
+        ext = [p.nx, p.ny] + ([p.nz] if p.lattice == D3Q19 else [])
+        return min(ext) // 2 + 1
+    return p.nx
 
 
 def _ptr(a):
@@ -366,7 +376,7 @@ class Sim:
 
     def scmc_observables(self, kind, R0=1.0):
         o = Obs()
-        n = self.p.nx // 2 + 1 if kind == OBS_DROPLET else self.p.nx
+        n = _profile_len(self.p, kind)
         PN = np.zeros(n)
         PT = np.zeros(n)
         self._check(lib().scmc_observables(self.h, kind, float(R0), ctypes.byref(o), _ptr(PN), _ptr(PT)),
@@ -487,7 +497,7 @@ class Batch:
     def scmc_batch_observables(self, i, kind, R0=1.0):
         o = Obs()
         p = self.problems[i]
-        n = p.nx // 2 + 1 if kind == OBS_DROPLET else p.nx
+        n = _profile_len(p, kind)
         PN, PT = np.zeros(n), np.zeros(n)
         self._check(lib().scmc_batch_observables(self.h, i, kind, float(R0), ctypes.byref(o),
                                                  _ptr(PN), _ptr(PT)), "scmc_batch_observables")
