@@ -49,12 +49,12 @@ TRACE_MD = os.path.join(ROOT, "profiles", "step_e6_f32_128cube_kernel_trace.md")
 # each pins its design, so that the trace and the counter runs profile the
 # same kernels (the autotuner's pick between the direct and the LDS-staged
 # pass 2 can differ from run to run): the LDS-staged pass 2 for the 16-bit
-# offsets (the pick of their bench variants), the direct one otherwise
+# formats (the pick of their bench variants), the direct one for FP32
 PROFILE_RUNS = {"f32": "--storage f32 --kernel two_pass_mom",
                 "f16_offset": "--storage f16_offset --kernel two_pass_mom --tile 64 8 8",
                 "bf16_offset": "--storage bf16_offset --kernel two_pass_mom --tile 64 8 8",
-                "f16_node": "--storage f16_node --kernel two_pass_mom",
-                "bf16_node": "--storage bf16_node --kernel two_pass_mom",
+                "f16_node": "--storage f16_node --kernel two_pass_mom --tile 64 8 8",
+                "bf16_node": "--storage bf16_node --kernel two_pass_mom --tile 64 8 8",
                 "batch48": "--batch-only"}
 
 
@@ -359,6 +359,7 @@ def variants(args, L, R0, bulk, init, dev, stream):
         a = acc.get("runs", {}).get(name, {})
         r["abs_err_R_s_vs_f64"] = a.get("abs_err_R_s")
         r["rel_err_sigma_s_vs_f64"] = a.get("rel_err_sigma_s")
+        r["abs_err_R_s_shell_vs_f64"] = a.get("abs_err_R_s_shell")
         c5[name] = r
     out[f"asym_{Lb}cube"] = c5
     out["batch48_f32"] = _batch_rate(args, bulk, bulk_asym, dev, stream, args.variant_steps)
@@ -575,9 +576,11 @@ def precision_study(args, out_md):
             step_ms += _timed_chunk(sim.scmc_step, k, stream)
             done += k
             o = sim.scmc_observables(scmc.OBS_DROPLET, R0)
+            osh = sim.scmc_observables(scmc.OBS_SHELL, R0)
             st = sim.scmc_stats_get()
             hist.append({"step": done, "dP": _finite(o["dP"]), "R_s": _finite(o["R_s"]),
-                         "sigma_s": _finite(o["sigma_s"]), "max_u": _finite(st["max_u"]),
+                         "sigma_s": _finite(o["sigma_s"]), "R_s_shell": _finite(osh["R_s"]),
+                         "sigma_s_shell": _finite(osh["sigma_s"]), "max_u": _finite(st["max_u"]),
                          "mass": st["mass"].tolist()})
             print(f"{name} step {done}: dP={o['dP']:.6g} R_s={o['R_s']:.6g} "
                   f"sigma_s={o['sigma_s']:.6g}", flush=True)
@@ -599,9 +602,12 @@ def precision_study(args, out_md):
              "Command (repository root, one MI355X):", "",
              "    python bench.py --precision profiles/precision_256cube_asym.md --size %d --steps %d"
              % (L, args.steps), "",
+             "The last two columns evaluate R_s on the shell-averaged profiles (observable "
+             "kind SHELL, a variant of the paper's axis line) of the same states, against "
+             "FP64's shell value.", "",
              "| storage | design | MLUPS | dP | R_s | sigma_s | abs err R_s | rel err sigma_s | "
-             "max abs err n on axis |",
-             "|---|---|---|---|---|---|---|---|---|"]
+             "max abs err n on axis | R_s (shells) | abs err R_s (shells) |",
+             "|---|---|---|---|---|---|---|---|---|---|---|"]
     out = {"workload": f"D3Q19 E6 {L}^3 B-rich droplet R0={R0:g} g_AA=-0.2", "steps": args.steps,
            "bulk": bulk.tolist() if hasattr(bulk, "tolist") else list(bulk), "runs": {}}
     for name, r in runs.items():
@@ -612,11 +618,15 @@ def precision_study(args, out_md):
               if f["sigma_s"] is not None and g["sigma_s"] else None)
         en = float(max(np.abs(r["axis_nA"] - ref["axis_nA"]).max(),
                        np.abs(r["axis_nB"] - ref["axis_nB"]).max()))
-        lines.append("| %s | %s | %.0f | %s | %s | %s | %s | %s | %.3g |" % (
+        eRs = (abs(f["R_s_shell"] - g["R_s_shell"])
+               if f["R_s_shell"] is not None and g["R_s_shell"] is not None else None)
+        lines.append("| %s | %s | %.0f | %s | %s | %s | %s | %s | %.3g | %s | %s |" % (
             name, r["kernel"], r["MLUPS"], _fmt(f["dP"], "%.8g"), _fmt(f["R_s"], "%.8g"),
-            _fmt(f["sigma_s"], "%.8g"), _fmt(eR, "%.3g"), _fmt(es, "%.3g"), en))
+            _fmt(f["sigma_s"], "%.8g"), _fmt(eR, "%.3g"), _fmt(es, "%.3g"), en,
+            _fmt(f["R_s_shell"], "%.8g"), _fmt(eRs, "%.3g")))
         out["runs"][name] = {"MLUPS": r["MLUPS"], "kernel": r["kernel"], "final": f,
-                             "abs_err_R_s": eR, "rel_err_sigma_s": es, "max_abs_err_n_axis": en}
+                             "abs_err_R_s": eR, "rel_err_sigma_s": es, "max_abs_err_n_axis": en,
+                             "abs_err_R_s_shell": eRs}
     lines += ["", "History of R_s (every 2^11 steps):", "",
               "| step | " + " | ".join(runs) + " |", "|---|" + "---|" * len(runs)]
     for i, h in enumerate(ref["hist"]):

@@ -76,7 +76,9 @@ __device__ __forceinline__ void pull64(const Member &m,
                     f[1][0] = (double)r.y;
                     continue;
                 }
-                const float2 q = m.ref[s];
+                // the offset pulled into (x, y, z) is taken from this node's
+                // own reference densities
+                const float2 q = m.ref[((long)z * m.ny + y) * m.nx + x];
                 const float w = (float)L::W[i];
                 f[0][i] = (double)ST::from_node(base[(long)i * m.N + s], node_ref(w, q.x));
                 f[1][i] = (double)ST::from_node(base[(long)(L::Q + i) * m.N + s], node_ref(w, q.y));

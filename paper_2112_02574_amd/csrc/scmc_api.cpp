@@ -520,8 +520,9 @@ int upload_state(Common &c, const Lat &L, const double *f, void *dst_dev) {
     std::vector<unsigned char> host(2 * q * N * sb);
     if (node_storage(p.storage)) {
         // the buffer value at node y is f*_i(y) = f_i(y + xi_i); its reference
-        // is the post-collision density of y, sum_i f*_i(y) (BGK conserves
-        // the node's mass, so this is n_J(y) of the step that produced it)
+        // is the density of the node it streams to, y + xi_i, with the
+        // post-collision density sum_k f*_k of a node (BGK conserves the
+        // node's mass, so this is n_J of the step that produced it)
         std::vector<double> nref(2 * N, 0.0);
         std::vector<float> ref(2 * N);
         auto src_of = [&](int i, int z, int y, int x) {
@@ -545,9 +546,10 @@ int upload_state(Common &c, const Lat &L, const double *f, void *dst_dev) {
                     for (int y = 0; y < p.ny; ++y)
                         for (int x = 0; x < p.nx; ++x) {
                             const size_t t = ((size_t)z * p.ny + y) * p.nx + x;
-                            const double v = f[((size_t)J * q + i) * N + src_of(i, z, y, x)];
+                            const size_t d = src_of(i, z, y, x);  // y + xi_i
+                            const double v = f[((size_t)J * q + i) * N + d];
                             h[((size_t)J * q + i) * N + t] =
-                                node_encode(p.storage, v, node_ref_host(w[i], ref[J * N + t]));
+                                node_encode(p.storage, v, node_ref_host(w[i], ref[J * N + d]));
                         }
         // reference field of buffer 0, as (n_A, n_B) pairs per node, and the
         // FP32 rest populations (the i = 0 planes of the buffer are unused)
@@ -638,9 +640,11 @@ int download_state(Common &c, const Lat &L, const void *src_dev, double *f) {
                         for (int x = 0; x < p.nx; ++x) {
                             const int xs = (x - xi[3 * i] + p.nx) % p.nx;
                             const size_t t = ((size_t)zs * p.ny + ys) * p.nx + xs;
-                            f[((size_t)J * q + i) * N + ((size_t)z * p.ny + y) * p.nx + x] =
+                            const size_t d = ((size_t)z * p.ny + y) * p.nx + x;
+                            // decoded against the densities of the pulling node
+                            f[((size_t)J * q + i) * N + d] =
                                 node_decode(p.storage, h[((size_t)J * q + i) * N + t],
-                                            node_ref_host(w[i], pairs[2 * t + J]));
+                                            node_ref_host(w[i], pairs[2 * d + J]));
                         }
                     }
         return SCMC_OK;

@@ -363,25 +363,30 @@ __device__ __forceinline__ void collide_tau1(const Member &m, const R (&mom)[NMO
 }
 
 // ---- per-node-reference offsets (FP16 / BF16 node storage): a population
-// collided at node x is stored as h = f* - w_i n_J(x), with n_J(x) the FP32
-// density of x, which a reference field keeps beside the buffer.  The
-// product and the sum are rounded on their own (no contraction into a fused
-// multiply-add), so that encoding, decoding and the mass closure agree bit
-// for bit wherever they are formed.
+// collided at node x, which streams to x + e_i, is stored as
+// h = f*_i - w_i n_J(x + e_i), with n_J the FP32 densities of the step (the
+// moments of its first pass), which a reference field keeps beside the
+// buffer.  The node that pulls it decodes it against its own densities, so
+// a pull reads one reference pair per node.  The product and the sum are
+// rounded on their own (no contraction into a fused multiply-add), so that
+// encoding, decoding and the mass closure agree bit for bit wherever they
+// are formed.
 __device__ __forceinline__ float node_ref(float w, float n) {
 #pragma clang fp contract(off)
     return w * n;
 }
 
-// The collision of a node-storage site: encodes the moving populations
-// against its own densities mom[0], mom[1] and closes the mass balance on
-// their decoded values, so the rest populations, kept in FP32 (restA, restB:
-// they do not stream), absorb the rounding of the 2Q - 2 moving offsets and
-// the node's mass is kept as with FP32 storage.
+// The collision of a node-storage site: encodes each moving population
+// against the densities nb[i] = (n_A, n_B)(x + e_i) of the node it streams
+// to and closes the mass balance on their decoded values, so the rest
+// populations, kept in FP32 (restA, restB: they do not stream), absorb the
+// rounding of the 2Q - 2 moving offsets and the node's mass is kept as with
+// FP32 storage.
 template <int D, class ST, class Sink>
 __device__ __forceinline__ void collide_tau1_node(const typename ST::R (&mom)[NMOM],
                                                   const typename ST::R (&FA)[3],
-                                                  const typename ST::R (&FB)[3], Sink &&sink,
+                                                  const typename ST::R (&FB)[3],
+                                                  const float2 (&nb)[Lattice<D>::Q], Sink &&sink,
                                                   float &restA, float &restB) {
     using L = Lattice<D>;
     using R = typename ST::R;
@@ -390,7 +395,7 @@ __device__ __forceinline__ void collide_tau1_node(const typename ST::R (&mom)[NM
             (J == 0 ? restA : restB) = v;
             return v;
         }
-        const R ref = node_ref((R)L::W[i], mom[J]);
+        const R ref = node_ref((R)L::W[i], J == 0 ? nb[i].x : nb[i].y);
         const typename ST::T h = ST::to_node(v, ref);
         sink(J, i, h);
         return ST::from_node(h, ref);
@@ -500,6 +505,8 @@ __device__ __forceinline__ void pull_site_buf(const Member &m, const PopBuf<ST> 
         zo[d + 1] = wrap1(z + d, m.nz) * nxy;
     }
     const R n0A = (R)m.n0[0], n0B = (R)m.n0[1];
+    float2 own = {0.f, 0.f};  // node storage: this node's reference densities
+    if constexpr (NODE) own = m.ref[zo[1] + yo[1] + xo[1]];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const int s = zo[1 - L::CZ[i]] + yo[1 - L::CY[i]] + xo[1 - L::CX[i]];
@@ -513,9 +520,8 @@ __device__ __forceinline__ void pull_site_buf(const Member &m, const PopBuf<ST> 
                 f[1][0] = r.y;
                 continue;
             }
-            const float2 q = m.ref[s];
-            refA = node_ref(w, q.x);
-            refB = node_ref(w, q.y);
+            refA = node_ref(w, own.x);
+            refB = node_ref(w, own.y);
         }
         const T ra = NT && L::CX[i] == 0 ? RawBuf<T>::load_nt(b.r[0], voff, soff)
                                          : RawBuf<T>::load(b.r[0], voff, soff);

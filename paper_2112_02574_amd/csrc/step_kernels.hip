@@ -251,9 +251,27 @@ __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopB
         });
     const int voff = s * (int)sizeof(T);
     if constexpr (NODE) {
+        // the densities of the nodes the populations stream to (x + e_i)
+        using L = Lattice<3>;
+        int xo[3], yo[3], zo[3];
+#pragma unroll
+        for (int d = -1; d <= 1; ++d) {
+            xo[d + 1] = wrap1(x + d, m.nx) * 8;
+            yo[d + 1] = wrap1(y + d, m.ny) * (m.nx * 8);
+            zo[d + 1] = wrap1(z + d, m.nz) * (m.nx * m.ny * 8);
+        }
+        float2 nb[L::Q];
+        nb[0] = float2{own.x, own.y};
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const auto q = __builtin_amdgcn_raw_buffer_load_b64(
+                pr, zo[1 + L::CZ[i]] + yo[1 + L::CY[i]] + xo[1 + L::CX[i]], 0, 0);
+            const unsigned qa = q[0], qb = q[1];
+            nb[i] = float2{__uint_as_float(qa), __uint_as_float(qb)};
+        }
         float2 r;
         collide_tau1_node<3, ST>(
-            mm, FA, FB,
+            mm, FA, FB, nb,
             [&](int J, int i, T h) { RawBuf<T>::store_nt(h, db.r[J], voff, i * db.plane_bytes); },
             r.x, r.y);
         m.rest[s] = r;
@@ -321,9 +339,15 @@ __global__ void __launch_bounds__(TX *TY)
             unpack_rem<R>(reinterpret_cast<const unsigned *>(base + 5 * (long)m.N)[s], mm);
             const int voff = s * (int)sizeof(T);
             if constexpr (NODE) {
+                // the densities of the nodes the populations stream to
+                using L = Lattice<3>;
+                float2 nb[L::Q];
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i)
+                    nb[i] = lds[(k - ZR + L::CZ[i]) % NSLOT][ty + HR + L::CY[i]][tx + HR + L::CX[i]];
                 float2 r;
                 collide_tau1_node<3, ST>(
-                    mm, FA, FB,
+                    mm, FA, FB, nb,
                     [&](int J, int i, T h) {
                         RawBuf<T>::store_nt(h, db.r[J], voff, i * db.plane_bytes);
                     },

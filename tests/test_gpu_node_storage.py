@@ -1,10 +1,11 @@
 """GPU parity of the FP16 / BF16 offsets from the per-node reference
 (storage F16_NODE / BF16_NODE) against the FP64 oracle.
 
-A population collided at node x is stored as h = f* - w_i n_J(x), with
-n_J(x) the FP32 density of x kept in a reference field beside the buffer
-(the equilibrium at rest of that node), rounded to 11 (FP16) or 8 (BF16)
-significant bits.  Each stored moving population therefore carries at most
+A population collided at node x, which streams to x + xi_i, is stored as
+h = f*_i - w_i n_J(x + xi_i), with n_J the FP32 densities of the step kept in
+a reference field beside the buffer (the equilibrium at rest of the node that
+pulls it, which decodes it against its own densities), rounded to 11 (FP16)
+or 8 (BF16) significant bits.  Each stored moving population therefore carries at most
 half an ulp of its own |h|; the rest population, kept in FP32 (it does not
 stream), closes the node's mass balance on the decoded values and so carries
 the rounding of the node's 18 moving offsets; a node of a bulk at rest
@@ -61,6 +62,14 @@ def _source_values(f):
     return out
 
 
+def _dest_density(n):
+    """n[J, z, y, x] -> n at the node each population streams to, x + xi_i,
+    indexed [J, i, z, y, x] by the collision node x."""
+    xi, _ = scmc.velocities(scmc.D3Q19)
+    return np.stack([np.roll(n, shift=(-xi[i, 2], -xi[i, 1], -xi[i, 0]), axis=(1, 2, 3))
+                     for i in range(19)], axis=1)
+
+
 def _bulk(g):
     return inputs.FLAT_GUESS[-0.2] if g[0][0] == -0.2 else inputs.FLAT_GUESS[0.0]
 
@@ -70,8 +79,8 @@ def _bulk(g):
 @pytest.mark.parametrize("storage", [scmc.F16_NODE, scmc.BF16_NODE])
 def test_node_storage_single_step(storage, design, g):
     """One step of a droplet (B-rich with g_AA = -0.2): every moving
-    population within half an ulp of its own offset from w_i n_J(source), the
-    rest population within the sum of its node's roundings."""
+    population within half an ulp of its own offset from w_i n_J(x + xi_i),
+    the rest population within the sum of its node's roundings."""
     print(f"node storage {storage} {design} g_AA {g[0][0]}", flush=True)
     shape = (10, 12, 66)
     nA, nB = inputs.droplet(66, 12, 10, R=5.0, a_rich=g[0][0] == 0.0, bulk=_bulk(g))
@@ -87,12 +96,12 @@ def test_node_storage_single_step(storage, design, g):
     perm = _perm()
     o = O.Oracle(3, 6, shape, g=g)
     o.set_populations(f0[:, np.argsort(perm)])
-    n_src = o.density()  # densities at t = 0: the references of the step's stores
+    n_dst = _dest_density(o.density())  # densities at t = 0 at x + xi_i: the stores' references
     o.run(1)
     fo = o.f[:, perm]
     _, w = scmc.velocities(scmc.D3Q19)
     star = _source_values(fo)                        # f*_i(x) by source node x
-    h = star - w[None, :, None, None, None] * n_src[:, None]
+    h = star - w[None, :, None, None, None] * n_dst
     hu = _half_ulp(h, storage)
     bound = hu.copy()
     bound[:, 0] = hu[:, 1:].sum(axis=1) + hu[:, 0]  # rest: the node's closure
