@@ -70,15 +70,17 @@ typedef enum {
     SCMC_F16_OFF = 2, /* stored as FP16 h = f - w_i n0_J (round to nearest
                          even), updated in FP32 */
     SCMC_BF16_OFF = 3, /* same with bfloat16 */
-    SCMC_F16_NODE = 4, /* stored as FP16 2^10 h, h = f* - w_i n_J(x) (round
-                          to nearest even; the exact power-of-two scale keeps
-                          offsets down to 2^-24 out of the FP16 subnormals),
-                          the offset from the equilibrium at
-                          rest of the node x where f* was collided: n_J(x)
-                          is that node's density, kept in FP32 beside the
-                          populations, so the stored offsets carry only the
-                          departure from rest (zero in a bulk at rest) and
-                          the minority phase keeps its precision.  The
+    SCMC_F16_NODE = 4, /* stored as FP16 2^10 h, h = f*_i(x) -
+                          w_i n_J(x + xi_i) (round to nearest even; the
+                          exact power-of-two scale keeps offsets down to
+                          2^-24 out of the FP16 subnormals), the offset from
+                          the equilibrium at rest of the node x + xi_i that
+                          pulls it: n_J is the density of the step, kept in
+                          FP32 beside the populations (the pulling node
+                          decodes against its own), so the stored offsets
+                          carry only the departure from rest (zero in a bulk
+                          at rest) and the minority phase keeps its
+                          precision.  The
                           rest populations, which do not stream, are kept
                           in FP32 and close each node's mass balance on the
                           decoded moving ones.  Updated in FP32.  D3Q19, tau =
@@ -207,9 +209,10 @@ int scmc_destroy(scmc_sim *s);
  * next step, the state is the first 2*Q*N values of the storage type at the
  * start of the workspace, laid out [J][i][z][y][x]; value (J, i, x) is the
  * post-collision f*_i^J(x) that the next step streams to x + xi_i (FP16 /
- * BF16: the offset f* - w_i n0_J; node storage: the offset f* - w_i n_J(x)
- * for i > 0, with the n_J(x) and the rest populations f*_0 held as FP32
- * pairs per node in the workspace's moment field).  scmc_step_static reads and writes buffers of
+ * BF16: the offset f* - w_i n0_J; node storage: the offset
+ * f*_i(x) - w_i n_J(x + xi_i) for i > 0, with the n_J and the rest
+ * populations f*_0 held as FP32 pairs per node in the workspace's moment
+ * field).  scmc_step_static reads and writes buffers of
  * this layout (node storage: SCMC_EUNSUPPORTED). */
 int scmc_set_density(scmc_sim *s, const double *nA, const double *nB);
 

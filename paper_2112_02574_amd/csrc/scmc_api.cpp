@@ -120,7 +120,7 @@ float f16_to_f32(uint16_t h) {
 float offset_ref(double w, double n0) { return (float)w * (float)n0; }
 
 // Node storage on the host, rounded as the kernels round: the reference
-// w_i n_J(x) and the decoded value are single-precision operations of their
+// w_i n_J and the decoded value are single-precision operations of their
 // own (no fused multiply-add).
 float node_ref_host(double w, float n) {
 #pragma clang fp contract(off)
