@@ -24,6 +24,7 @@ storage formats (FP64, FP16 and BF16 offsets) on the same droplet and of the
 timed run.
 """
 import argparse
+import csv
 import hashlib
 import json
 import math
@@ -240,6 +241,108 @@ def summarize_profiles(outdir, tag="f32", L=128):
     with open(trace_md, "w") as fh:
         fh.write("\n".join(lines))
     print(open(trace_md).read())
+
+
+# the FP32 designs compared at 128^3: kernel trace, FETCH/WRITE traffic and
+# the SQ instruction mix of each (profiles/step_e6_f32_128cube_designs.md)
+DESIGN_RUNS = {"two_pass_mom": "--storage f32 --kernel two_pass_mom",
+               "two_pass_mom_lds": "--storage f32 --kernel two_pass_mom --tile 64 8 8",
+               "fused_mom": "--storage f32 --kernel fused_mom --tile 128 4 16",
+               "two_pass": "--storage f32 --kernel two_pass"}
+SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR "
+               "SQ_INSTS_SALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES")
+
+
+def design_profile_commands(name):
+    run = DESIGN_RUNS[name]
+    base = "python3 bench.py --steps 20 --warmup 5 --cpu-steps 0 --variant-steps 0 --init tanh " + run
+    return {
+        "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/dprof_{name}_trace "
+                 f"-o trace -- python3 bench.py --steps 300 --warmup 20 --cpu-steps 0 --variant-steps 0 "
+                 f"--init tanh {run}",
+        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/dprof_{name}_fetch -o fetch -- {base}",
+        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/dprof_{name}_write -o write -- {base}",
+        "sq": f"rocprofv3 --pmc {SQ_COUNTERS} --output-format csv -d gpurun_out/dprof_{name}_sq -o sq -- {base}",
+    }
+
+
+def summarize_designs(outdir, L=128):
+    """profiles/step_e6_f32_128cube_designs.md from the design_profile_commands
+    outputs (and the copy calibration of the FP32 profile)."""
+    N = L ** 3
+
+    def rows(sub, suffix):
+        d = os.path.join(outdir, sub)
+        name = [f for f in os.listdir(d) if f.endswith(suffix)][0]
+        return list(csv.DictReader(open(os.path.join(d, name))))
+
+    def mean_by_kernel(sub):
+        acc = {}
+        for r in rows(sub, "_counter_collection.csv"):
+            k = r["Kernel_Name"].split("(")[0]
+            acc.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+
+    cf = mean_by_kernel("prof_copy_fetch")["__amd_rocclr_copyBuffer"]["FETCH_SIZE"]
+    cw = mean_by_kernel("prof_copy_write")["__amd_rocclr_copyBuffer"]["WRITE_SIZE"]
+    sf, sw = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
+    lines = ["# FP32 step designs on the 128^3 droplet: time, traffic, instruction mix", "",
+             "D3Q19 E6 droplet 128^3, FP32 populations, tau = 1. Per step kernel: the mean duration "
+             "of the trace run, its LDS per workgroup, HBM traffic from FETCH_SIZE / WRITE_SIZE "
+             "scaled by a 1 GiB copy (FETCH x%.3f, WRITE x%.3f), and the instructions the SQ counters "
+             "count per 64 sites (one wavefront's worth; the designs give a wavefront different "
+             "numbers of sites)." % (sf, sw), "",
+             "| design | kernel | us | LDS B/WG | HBM MB | VALU | LDS | VMEM rd | VMEM wr | SALU |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    summary = []
+    copy_line = None
+    for name in DESIGN_RUNS:
+        cmds = design_profile_commands(name)
+        trace = rows(f"dprof_{name}_trace", "_kernel_trace.csv")
+        stats = rows(f"dprof_{name}_trace", "_kernel_stats.csv")
+        fetch, write, sq = (mean_by_kernel(f"dprof_{name}_{k}") for k in ("fetch", "write", "sq"))
+        step_us = hbm = 0.0
+        for st in stats:
+            k = st["Name"].split("(")[0]
+            if "k_pull_copy<3, float>" in k and copy_line is None:
+                us = float(st["AverageNs"]) / 1e3
+                copy_line = (us, 304 * N / (us * 1e-6) / 1e9)
+            if not STEP_KERNEL.search(k) or "density64" in k or "kb_" in k:
+                continue
+            t = next(r for r in trace if r["Kernel_Name"].split("(")[0] == k)
+            lds = int(t["LDS_Block_Size"])
+            us = float(st["AverageNs"]) / 1e3
+            h = (fetch.get(k, {}).get("FETCH_SIZE", 0) * sf + write.get(k, {}).get("WRITE_SIZE", 0) * sw) * 1024
+            q = sq.get(k, {})
+            per = N / 64.0
+            step_us += us
+            hbm += h
+            lines.append("| %s | `%s` | %.1f | %d | %.0f | %.0f | %.0f | %.1f | %.1f | %.0f |" % (
+                name, k.replace("void scmc::", ""), us, lds, h / 1e6,
+                q.get("SQ_INSTS_VALU", 0) / per, q.get("SQ_INSTS_LDS", 0) / per,
+                q.get("SQ_INSTS_VMEM_RD", 0) / per, q.get("SQ_INSTS_VMEM_WR", 0) / per,
+                q.get("SQ_INSTS_SALU", 0) / per))
+        summary.append((name, step_us, hbm, cmds))
+    lines += ["", "| design | us per step | MLUPS | % of 8 TB/s at 304 B/site | HBM bytes / algorithmic |",
+              "|---|---|---|---|---|"]
+    for name, us, hbm, _ in summary:
+        lines.append("| %s | %.1f | %.0f | %.1f | %.3f |" % (
+            name, us, N / us, 304 * N / (us * 1e-6) / 8e12 * 100, hbm / (304 * N)))
+    if copy_line:
+        lines += ["", "Copy ceiling: `scmc_pull_copy` (the populations of one buffer copied to the other "
+                  "with the pull shifts, one site per lane, the step's access pattern without its "
+                  "arithmetic) takes %.1f us on the same buffers: %.0f GB/s, %.1f%% of 8 TB/s. "
+                  "It runs after the timed steps of the first design's trace run." % (
+                      copy_line[0], copy_line[1], copy_line[1] / 80)]
+    lines += ["", "Commands (repository root, one MI355X), per design:", ""]
+    for name, _, _, cmds in summary:
+        for k in ("trace", "fetch", "write", "sq"):
+            lines.append("    " + cmds[k])
+    lines += ["", "Copy calibration: as in step_e6_f32_128cube_traffic.txt.", ""]
+    out = os.path.join(ROOT, "profiles", "step_e6_f32_128cube_designs.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print(open(out).read())
 
 
 def cpu_baseline(L, R0, steps, steps_1t):
@@ -775,6 +878,9 @@ def main():
     ap.add_argument("--tolman-max-steps", type=int, default=400000)
     ap.add_argument("--summarize", metavar="DIR", default=None,
                     help="only write the profiles/ summaries from rocprofv3 output in DIR")
+    ap.add_argument("--summarize-designs", metavar="OUTDIR", default=None,
+                    help="write profiles/step_e6_f32_128cube_designs.md from the outputs of "
+                         "design_profile_commands under OUTDIR")
     ap.add_argument("--summarize-tags", default="f32",
                     help="comma-separated profiled workloads to summarize (" + ",".join(PROFILE_RUNS) + ")")
     ap.add_argument("--storage", choices=sorted(STORAGE_BYTES), default="f32",
@@ -784,6 +890,9 @@ def main():
     args = ap.parse_args()
     if args.precision:
         precision_study(args, args.precision)
+        return
+    if args.summarize_designs:
+        summarize_designs(args.summarize_designs, args.size)
         return
     if args.summarize:
         for tag in args.summarize_tags.split(","):
