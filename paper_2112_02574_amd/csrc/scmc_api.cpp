@@ -329,6 +329,7 @@ StepKey key_of(const scmc_problem &p) {
     k.order = p.stencil;
     k.storage = storage_kind(p.storage);
     k.node = node_storage(p.storage) ? 1 : 0;
+    k.sr = p.rounding == SCMC_ROUND_STOCHASTIC ? 1 : 0;
     k.psi = p.psi_self;
     switch (p.kernel) {
         case SCMC_KERNEL_FUSED_REPULL: k.repull = 1; break;

@@ -62,6 +62,9 @@ struct StepKey {
                      // 32-bit buffer offsets (fused designs unavailable)
     int node = 0;    // FP16 / BF16 offsets from the per-node reference
                      // (moment two-pass, D3Q19 buffer forms only)
+    int sr = 0;      // 1 = stochastic rounding of the 16-bit offsets: the
+                     // buffer forms' collision passes are compiled with and
+                     // without it (its generator costs registers)
 };
 
 // ---- step kernels (step_kernels.hip)

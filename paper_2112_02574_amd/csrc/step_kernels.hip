@@ -222,7 +222,9 @@ __device__ __forceinline__ void moments_site_buf(const Member &m, const PopBuf<S
     reinterpret_cast<unsigned *>(base + 5 * (long)m.N)[s] = pack_rem<R>(mm);
 }
 
-template <int ORDER, class ST, int PSI, bool NODE = false>
+// SR: stores rounded stochastically (16-bit offsets, every member of the
+// launch); without it the generator is compiled out.
+template <int ORDER, class ST, int PSI, bool NODE = false, bool SR = false>
 __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopBuf<ST> &db,
                                                      const typename ST::R *__restrict__ mom,
                                                      int x, int y, int z) {
@@ -277,7 +279,7 @@ __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopB
         m.rest[s] = r;
         return;
     }
-    if (m.sr) {
+    if constexpr (SR) {
         SiteRng rng(m.seed, *m.step_ctr, (unsigned)(m.pop_off + s));
         collide_tau1<3, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
             RawBuf<T>::store_nt(ST::to_raw_sr(v, ref, rng.next()), db.r[J], voff,
@@ -295,7 +297,8 @@ __device__ __forceinline__ void collide_mom_site_buf(const Member &m, const PopB
 // a ring of 2 ZR + 2 pair planes (tile + halo, 8 B per node, coalesced), so
 // every pair is fetched about once per chunk instead of once per stencil
 // neighbour; the node's momentum and remainders are read directly.
-template <int TX, int TY, int ZC, int ORDER, class ST, int PSI, bool NODE = false>
+template <int TX, int TY, int ZC, int ORDER, class ST, int PSI, bool NODE = false,
+          bool SR = false>
 __global__ void __launch_bounds__(TX *TY)
     k_collide_mom_lds(Member m, const typename ST::T *__restrict__ src,
                       typename ST::T *__restrict__ dst,
@@ -353,7 +356,7 @@ __global__ void __launch_bounds__(TX *TY)
                     },
                     r.x, r.y);
                 m.rest[s] = r;
-            } else if (m.sr) {
+            } else if constexpr (SR) {
                 SiteRng rng(m.seed, *m.step_ctr, (unsigned)(m.pop_off + s));
                 collide_tau1<3, R>(m, mm, FA, FB, [&](int J, int i, R v, R ref) {
                     RawBuf<T>::store_nt(ST::to_raw_sr(v, ref, rng.next()), db.r[J], voff,
@@ -378,7 +381,7 @@ __global__ void __launch_bounds__(BLK)
     if (linear_site<BLK>(m, x, y, z)) moments_site_buf<ST, NODE>(m, sb, mom, x, y, z);
 }
 
-template <int ORDER, class ST, int PSI, int BLK, bool NODE = false>
+template <int ORDER, class ST, int PSI, int BLK, bool NODE = false, bool SR = false>
 __global__ void __launch_bounds__(BLK)
     k_collide_mom_buf(Member m, const typename ST::T *__restrict__ src,
                       typename ST::T *__restrict__ dst,
@@ -386,7 +389,7 @@ __global__ void __launch_bounds__(BLK)
     const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
     int x, y, z;
     if (linear_site<BLK>(m, x, y, z))
-        collide_mom_site_buf<ORDER, ST, PSI, NODE>(m, db, mom, x, y, z);
+        collide_mom_site_buf<ORDER, ST, PSI, NODE, SR>(m, db, mom, x, y, z);
 }
 
 // Block b of a launch that runs n2 blocks of pass 2 and n1 of pass 1: groups
@@ -443,7 +446,7 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-template <int ORDER, class ST, int PSI>
+template <int ORDER, class ST, int PSI, bool SR = false>
 __global__ void __launch_bounds__(256)
     kb_collide_mom_buf(const Member *__restrict__ members, const Tile *__restrict__ tiles,
                        int ntiles, const typename ST::T *__restrict__ src,
@@ -454,7 +457,8 @@ __global__ void __launch_bounds__(256)
         const Member m = members[tl.member];
         const PopBuf<ST> db = make_popbuf<ST, 19>(dst, m);
         int x, y, z;
-        if (tile_site(m, tl, x, y, z)) collide_mom_site_buf<ORDER, ST, PSI>(m, db, mom, x, y, z);
+        if (tile_site(m, tl, x, y, z))
+            collide_mom_site_buf<ORDER, ST, PSI, false, SR>(m, db, mom, x, y, z);
     }
 }
 
@@ -598,6 +602,8 @@ template <int D, class ST> constexpr bool buf_form() {
 template <int D, class ST> constexpr bool node_form() {
     return buf_form<D, ST>() && sizeof(typename ST::T) == 2;
 }
+// stochastic rounding: the 16-bit offset formats
+template <class ST> constexpr bool sr_form() { return sizeof(typename ST::T) == 2; }
 
 // The LDS-staged collision pass (StepKey::mom == 2) marches 64 x 8 columns
 // through z-chunks of 8 planes (measured on 128^3).
@@ -678,8 +684,8 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
             const dim3 g(linear_blocks(m, m.znum, LIN_BLOCK)), b(LIN_BLOCK, 1, 1);
             bool done = false;
             if constexpr (buf_form<D, ST>()) {
-                auto go = [&](auto Nc) {
-                    constexpr bool NODE = decltype(Nc)::value;
+                auto go = [&](auto Nc, auto Sc) {
+                    constexpr bool NODE = decltype(Nc)::value, SR = decltype(Sc)::value;
                     const std::vector<SlabOp> slabs = slab_schedule(k, m);
                     if (!slabs.empty()) {
                         const dim3 b(SLAB_BLOCK, 1, 1);
@@ -713,19 +719,21 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
                                            (const T *)src, (R *)dens);
                         if (k.mom == 2)
                             hipLaunchKernelGGL(
-                                (k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P, NODE>), gc, bc, 0,
-                                st, m, (const T *)src, (T *)dst, (const R *)dens);
+                                (k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P, NODE, SR>), gc,
+                                bc, 0, st, m, (const T *)src, (T *)dst, (const R *)dens);
                         else
-                            hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P, LIN_BLOCK, NODE>), gc,
-                                               bc, 0, st, m, (const T *)src, (T *)dst,
+                            hipLaunchKernelGGL((k_collide_mom_buf<O, ST, P, LIN_BLOCK, NODE, SR>),
+                                               gc, bc, 0, st, m, (const T *)src, (T *)dst,
                                                (const R *)dens);
                         done = true;
                     }
                 };
                 if (k.node) {
-                    if constexpr (node_form<D, ST>()) go(std::true_type{});
+                    if constexpr (node_form<D, ST>()) go(std::true_type{}, std::false_type{});
+                } else if (k.sr) {
+                    if constexpr (sr_form<ST>()) go(std::false_type{}, std::true_type{});
                 } else {
-                    go(std::false_type{});
+                    go(std::false_type{}, std::false_type{});
                 }
             }
             if (done) {
@@ -765,12 +773,13 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dn, NodeLaunch *sn,
             dn->block = sn->block = dim3(LIN_BLOCK, 1, 1);
             dn->shmem = sn->shmem = 0;
             if constexpr (buf_form<D, ST>()) {
-                auto set = [&](auto Nc) {
-                    constexpr bool NODE = decltype(Nc)::value;
+                auto set = [&](auto Nc, auto Sc) {
+                    constexpr bool NODE = decltype(Nc)::value, SR = decltype(Sc)::value;
                     dn->func = (void *)&k_moments_buf<ST, LIN_BLOCK, NODE>;
-                    sn->func = k.mom == 2
-                                   ? (void *)&k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P, NODE>
-                                   : (void *)&k_collide_mom_buf<O, ST, P, LIN_BLOCK, NODE>;
+                    sn->func =
+                        k.mom == 2
+                            ? (void *)&k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P, NODE, SR>
+                            : (void *)&k_collide_mom_buf<O, ST, P, LIN_BLOCK, NODE, SR>;
                     mom_blocks(m, k.mom == 2, &dn->grid, &dn->block, &sn->grid, &sn->block);
                     if (!slab_schedule(k, m).empty()) {  // slab launches: grid set per slab
                         dn->func = (void *)&k_moments_buf<ST, SLAB_BLOCK, NODE>;
@@ -779,10 +788,12 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dn, NodeLaunch *sn,
                     }
                 };
                 if (k.mom && !k.big) {
-                    if (!k.node) {
-                        set(std::false_type{});
-                    } else if constexpr (node_form<D, ST>()) {
-                        set(std::true_type{});
+                    if (k.node) {
+                        if constexpr (node_form<D, ST>()) set(std::true_type{}, std::false_type{});
+                    } else if (k.sr) {
+                        if constexpr (sr_form<ST>()) set(std::false_type{}, std::true_type{});
+                    } else {
+                        set(std::false_type{}, std::false_type{});
                     }
                 }
             }
@@ -859,10 +870,20 @@ hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
                         hipLaunchKernelGGL((kb_moments_buf<ST>), dim3(grid), b, 0, st,
                                            d_members, d_tiles, ntiles, (const T *)src,
                                            (R *)dens);
-                    if (p2)
+                    if (p2 && k.sr) {
+                        if constexpr (!sr_form<ST>()) {
+                            err = hipErrorNotSupported;
+                            return;
+                        } else {
+                            hipLaunchKernelGGL((kb_collide_mom_buf<O, ST, P, true>), dim3(grid), b,
+                                               0, st, d_members, d_tiles, ntiles, (const T *)src,
+                                               (T *)dst, (const R *)dens);
+                        }
+                    } else if (p2) {
                         hipLaunchKernelGGL((kb_collide_mom_buf<O, ST, P>), dim3(grid), b, 0,
                                            st, d_members, d_tiles, ntiles, (const T *)src,
                                            (T *)dst, (const R *)dens);
+                    }
                     done = true;
                 }
             }
@@ -908,6 +929,8 @@ bool node_batch_two_pass(const StepKey &k, int grid, NodeLaunch *dn,
                 if (k.mom && !k.big) {
                     dn->func = (void *)&kb_moments_buf<ST>;
                     sn->func = (void *)&kb_collide_mom_buf<O, ST, P>;
+                    if constexpr (sr_form<ST>())
+                        if (k.sr) sn->func = (void *)&kb_collide_mom_buf<O, ST, P, true>;
                 }
             }
             dn->grid = sn->grid = dim3(grid);

@@ -757,6 +757,38 @@ def test_stochastic_rounding_graph_replay(tile):
     assert np.array_equal(fa, fd)
 
 
+def test_stochastic_rounding_batch():
+    """A batch draws each member's rounding stream from its seed, the shared
+    step counter and the member's offset in the batch buffers: member 0 (at
+    offset 0) gives the bits of the same problem run alone, and member 1 does
+    round stochastically (it differs from nearest-even rounding, by a few
+    ulp of the offsets)."""
+    shapes = [(16, 20, 24), (12, 16, 20)]
+    ps = [scmc.problem(scmc.D3Q19, scmc.E6, sh, storage=scmc.F16_OFF,
+                       kernel=scmc.KERNEL_TWO_PASS_MOM, rounding=scmc.ROUND_STOCHASTIC, seed=5)
+          for sh in shapes]
+    dens = [inputs.droplet(*sh[::-1], R=4.0) for sh in shapes]
+    bt = scmc.Batch(ps)
+    for i, d in enumerate(dens):
+        bt.scmc_batch_set_density(i, *d)
+    bt.scmc_batch_step(9)
+    a = scmc.Sim(ps[0])
+    a.scmc_set_density(*dens[0])
+    a.scmc_step(9)
+    fa, sa = a.scmc_get_populations()
+    fb, sb = bt.scmc_batch_get_populations(0)
+    assert sa == sb == 9 and np.array_equal(fa, fb)
+    n = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, shapes[1], storage=scmc.F16_OFF,
+                              kernel=scmc.KERNEL_TWO_PASS_MOM))
+    n.scmc_set_density(*dens[1])
+    n.scmc_step(9)
+    fn, _ = n.scmc_get_populations()
+    f1, _ = bt.scmc_batch_get_populations(1)
+    assert not np.array_equal(f1, fn) and np.abs(f1 - fn).max() < 1e-2
+    for s in (a, n, bt):
+        s.close()
+
+
 @pytest.mark.parametrize("design", ["two_pass", "auto", "fused"])
 @pytest.mark.parametrize("storage,tol", [(scmc.F64, 1e-12), (scmc.F32, 4e-6)])
 @pytest.mark.parametrize("case", [2, 4, 5])
