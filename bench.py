@@ -488,6 +488,9 @@ def _batch_rate(args, bulk, bulk_asym, dev, stream, steps, graph=64):
         b.scmc_batch_set_density(i, *inputs.droplet(Lm, Lm, Lm, R=m["R0"], a_rich=m["a_rich"],
                                                     bulk=bulks[m["g"][0][0]]))
     b.scmc_batch_set_graph_steps(graph)
+    # untimed: the first run of `graph` steps captures and instantiates the
+    # graph (72 launches per step), a one-time cost outside the step rate
+    b.scmc_batch_step(max(graph, 1))
     ms = _timed(b.scmc_batch_step, steps, stream)
     sites = sum(m["L"] ** 3 for m in members)
     gbs = 4 * 19 * 4 * sites / (ms * 1e-3) / 1e9

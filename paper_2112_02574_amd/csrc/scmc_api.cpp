@@ -211,9 +211,10 @@ struct scmc_sim {
 };
 
 // One launch of the batched two-pass: pass 1 or 2 over tiles [t0, t0 + n),
-// one workgroup per tile.
+// one workgroup per tile; nt_all: pass 1 with every load non-temporal.
 struct BatchOp {
     int pass, t0, n;
+    bool nt_all = false;
 };
 
 struct scmc_batch {
@@ -865,7 +866,7 @@ int direct_step_batch(scmc_batch *b) {
     for (size_t k = 0; e == hipSuccess && k < b->ops.size(); ++k) {
         const BatchOp &o = b->ops[k];
         e = launch_batch_two_pass(c.key, b->d_members, b->d_tiles + o.t0, o.n, src, dst, c.dens,
-                                  o.n, c.stream, o.pass);
+                                  o.n, c.stream, o.pass, o.nt_all);
     }
     if (e != hipSuccess)
         return fail(c, SCMC_EDEVICE, "batch step launch: %s",
@@ -913,8 +914,8 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
     int cur = par, rc = SCMC_OK;
     for (int t = 0; t < k && !rc; ++t) {
         if (ops) {  // the two-pass launches of direct_step_batch
-            NodeLaunch dn{}, sn{};
-            if (!node_batch_two_pass(c.key, 1, &dn, &sn)) {
+            NodeLaunch dn{}, sn{}, dna{};
+            if (!node_batch_two_pass(c.key, 1, &dn, &sn, &dna)) {
                 rc = fail(c, SCMC_EUNSUPPORTED, "no graph node for this kernel");
                 break;
             }
@@ -932,7 +933,7 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
                 if (rc) break;
                 dt = d_tiles + o.t0;
                 nt = o.n;
-                NodeLaunch nl = o.pass == 1 ? dn : sn;
+                NodeLaunch nl = o.pass == 1 ? (o.nt_all ? dna : dn) : sn;
                 nl.grid = dim3(nt);  // one workgroup per tile
                 rc = add(nl, o.pass == 1 ? dargs : sargs);
             }
@@ -1606,8 +1607,12 @@ static void batch_set_ops(scmc_batch *b) {
         int t = 0;
         for (const std::vector<int> &chunk : two_pass_chunks(ps)) {
             int n = 0;
-            for (int i : chunk) n += (b->lats[i].m.N + 255) / 256;  // tiles of batch_tiles
-            ops.push_back({1, t, n});
+            long sites = 0;
+            for (int i : chunk) {
+                n += (b->lats[i].m.N + 255) / 256;  // tiles of batch_tiles
+                sites += b->lats[i].m.N;
+            }
+            ops.push_back({1, t, n, pass1_nt_all(c.key, sites)});
             ops.push_back({2, t, n});
             t += n;
         }

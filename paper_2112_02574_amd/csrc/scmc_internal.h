@@ -83,11 +83,16 @@ bool fused_supported(const StepKey &k, const int *tile);
 // two-pass batched launches run one workgroup per 256-site tile.)
 int resident_blocks(const void *f, int threads, unsigned shmem = 0);
 // grid: workgroups; one per tile runs each tile once.  passes: 1 = pass 1
-// only, 2 = pass 2 only, 3 = both
+// only, 2 = pass 2 only, 3 = both.  nt_all: pass 1 loads every population
+// non-temporally (FP32 moment two-pass; see pass1_nt_all)
 hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
                                  const Tile *d_tiles, int ntiles,
                                  const void *src, void *dst, void *dens,
-                                 int grid, hipStream_t st, int passes = 3);
+                                 int grid, hipStream_t st, int passes = 3,
+                                 bool nt_all = false);
+// Whether pass 1 of the moment two-pass over `sites` sites (one unslabbed
+// lattice, or one chunk of a batch) loads every population non-temporally.
+bool pass1_nt_all(const StepKey &k, long sites);
 
 hipError_t launch_batch_fused(const StepKey &k, const Member *d_members,
                               const Tile *d_tiles, int ntiles, const void *src,
@@ -118,8 +123,10 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dens_node,
                    NodeLaunch *step_node, const Member &m);
 bool node_fused(const StepKey &k, const int *tile, NodeLaunch *node,
                 const Member &m);
+// dens_node_nt_all (optional): the pass-1 node of launch_batch_two_pass's
+// nt_all form (the same as dens_node where there is none)
 bool node_batch_two_pass(const StepKey &k, int grid, NodeLaunch *dens_node,
-                         NodeLaunch *step_node);
+                         NodeLaunch *step_node, NodeLaunch *dens_node_nt_all = nullptr);
 bool node_batch_fused(const StepKey &k, const int *tile, int grid,
                       NodeLaunch *node);
 

@@ -486,10 +486,18 @@ __device__ __forceinline__ PopBuf<ST> make_popbuf(const typename ST::T *pop,
     return b;
 }
 
-// Pull of site (x, y, z) through buffer descriptors (D3Q19); NT as in
-// pull_site.  NODE: the buffer holds per-node-reference offsets, decoded
+// Cache policy of a pull through buffer descriptors.  PULL_NT_ALIGNED: the
+// populations with xi_x = 0 are loaded non-temporally, as pull_site's NT.
+// PULL_NT_ALL: every population is, so that the populations streaming
+// through pass 1 of the moment two-pass push less of the moment field it
+// writes out of the Infinity Cache before pass 2 reads it (lattices whose
+// moment field comes close to that cache's size).
+enum PullPolicy : int { PULL_CACHED = 0, PULL_NT_ALIGNED = 1, PULL_NT_ALL = 2 };
+
+// Pull of site (x, y, z) through buffer descriptors (D3Q19); NT is a
+// PullPolicy.  NODE: the buffer holds per-node-reference offsets, decoded
 // against the reference densities m.ref of the source nodes.
-template <class ST, bool NT = false, bool NODE = false>
+template <class ST, int NT = PULL_CACHED, bool NODE = false>
 __device__ __forceinline__ void pull_site_buf(const Member &m, const PopBuf<ST> &b,
                                               int x, int y, int z,
                                               typename ST::R (&f)[2][19]) {
@@ -523,10 +531,11 @@ __device__ __forceinline__ void pull_site_buf(const Member &m, const PopBuf<ST> 
             refA = node_ref(w, own.x);
             refB = node_ref(w, own.y);
         }
-        const T ra = NT && L::CX[i] == 0 ? RawBuf<T>::load_nt(b.r[0], voff, soff)
-                                         : RawBuf<T>::load(b.r[0], voff, soff);
-        const T rb = NT && L::CX[i] == 0 ? RawBuf<T>::load_nt(b.r[1], voff, soff)
-                                         : RawBuf<T>::load(b.r[1], voff, soff);
+        const bool nt = NT == PULL_NT_ALL || (NT == PULL_NT_ALIGNED && L::CX[i] == 0);
+        const T ra = nt ? RawBuf<T>::load_nt(b.r[0], voff, soff)
+                        : RawBuf<T>::load(b.r[0], voff, soff);
+        const T rb = nt ? RawBuf<T>::load_nt(b.r[1], voff, soff)
+                        : RawBuf<T>::load(b.r[1], voff, soff);
         if constexpr (NODE) {
             f[0][i] = ST::from_node(ra, refA);
             f[1][i] = ST::from_node(rb, refB);

@@ -205,14 +205,14 @@ __device__ __forceinline__ void collide_mom_site(const Member &m,
 // 2 GiB): plane offsets go in the scalar offset, lanes carry 32-bit offsets.
 // The (n_A, n_B) pairs sit at slot m.pair_slot of the moment field (0 but
 // for node storage, whose pass 1 writes the pairs into the reference field
-// of the buffer that pass 2 fills).
-template <class ST, bool NODE = false>
+// of the buffer that pass 2 fills).  NT: the pull's PullPolicy.
+template <class ST, bool NODE = false, int NT = PULL_NT_ALIGNED>
 __device__ __forceinline__ void moments_site_buf(const Member &m, const PopBuf<ST> &sb,
                                                  typename ST::R *__restrict__ mom, int x,
                                                  int y, int z) {
     using R = typename ST::R;
     R f[2][19], mm[NMOM];
-    pull_site_buf<ST, true, NODE>(m, sb, x, y, z, f);
+    pull_site_buf<ST, NT, NODE>(m, sb, x, y, z, f);
     site_moments<3, R>(f, mm);
     const int s = (z * m.ny + y) * m.nx + x;
     R *base = mom + m.dens_off;
@@ -371,14 +371,14 @@ __global__ void __launch_bounds__(TX *TY)
     }
 }
 
-template <class ST, int BLK, bool NODE = false>
+template <class ST, int BLK, bool NODE = false, int NT = PULL_NT_ALIGNED>
 __global__ void __launch_bounds__(BLK)
     k_moments_buf(Member m, const typename ST::T *__restrict__ src,
                   typename ST::R *__restrict__ mom) {
     advance_step_counter(m, blockIdx.x == 0);
     const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
     int x, y, z;
-    if (linear_site<BLK>(m, x, y, z)) moments_site_buf<ST, NODE>(m, sb, mom, x, y, z);
+    if (linear_site<BLK>(m, x, y, z)) moments_site_buf<ST, NODE, NT>(m, sb, mom, x, y, z);
 }
 
 template <int ORDER, class ST, int PSI, int BLK, bool NODE = false, bool SR = false>
@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(BLK)
     }
 }
 
-template <class ST>
+template <class ST, int NT = PULL_NT_ALIGNED>
 __global__ void __launch_bounds__(256)
     kb_moments_buf(const Member *__restrict__ members, const Tile *__restrict__ tiles,
                    int ntiles, const typename ST::T *__restrict__ src,
@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(256)
         advance_step_counter(m, t == 0);
         const PopBuf<ST> sb = make_popbuf<ST, 19>(src, m);
         int x, y, z;
-        if (tile_site(m, tl, x, y, z)) moments_site_buf<ST>(m, sb, mom, x, y, z);
+        if (tile_site(m, tl, x, y, z)) moments_site_buf<ST, false, NT>(m, sb, mom, x, y, z);
     }
 }
 
@@ -604,6 +604,23 @@ template <int D, class ST> constexpr bool node_form() {
 }
 // stochastic rounding: the 16-bit offset formats
 template <class ST> constexpr bool sr_form() { return sizeof(typename ST::T) == 2; }
+// pass 1 with every load non-temporal: FP32 populations, global reference
+template <class ST, bool NODE> constexpr bool nt_all_form() {
+    return !NODE && std::is_same<ST, StoreF32>::value;
+}
+
+// Pass 1 of an unslabbed FP32 moment two-pass loads every population
+// non-temporally once the moment fields it writes reach kNtAllMomentBytes.
+// Below that they stay cached between the passes either way, and the
+// shifted populations' lines, which neighbouring wavefronts share, are worth
+// keeping in L2 (measured: 4-7 % slower steps at 128^3-144^3 with every load
+// non-temporal, 1-11 % faster ones at 152^3-168^3).
+static constexpr size_t kNtAllMomentBytes = (size_t)80 << 20;
+
+bool pass1_nt_all(const StepKey &k, long sites) {
+    return k.storage == ST_F32 && k.mom && !k.node && !k.big &&
+           (size_t)sites * 24 >= kNtAllMomentBytes;
+}
 
 // The LDS-staged collision pass (StepKey::mom == 2) marches 64 x 8 columns
 // through z-chunks of 8 planes (measured on 128^3).
@@ -715,8 +732,14 @@ hipError_t launch_two_pass(const StepKey &k, const Member &m, const void *src,
                     } else if (k.mom && !k.big) {
                         dim3 gm, bm, gc, bc;
                         mom_blocks(m, k.mom == 2, &gm, &bm, &gc, &bc);
-                        hipLaunchKernelGGL((k_moments_buf<ST, LIN_BLOCK, NODE>), gm, bm, 0, st, m,
-                                           (const T *)src, (R *)dens);
+                        bool nt_all = false;
+                        if constexpr (nt_all_form<ST, NODE>()) nt_all = pass1_nt_all(k, m.N);
+                        if (nt_all)
+                            hipLaunchKernelGGL((k_moments_buf<ST, LIN_BLOCK, false, PULL_NT_ALL>),
+                                               gm, bm, 0, st, m, (const T *)src, (R *)dens);
+                        else
+                            hipLaunchKernelGGL((k_moments_buf<ST, LIN_BLOCK, NODE>), gm, bm, 0, st,
+                                               m, (const T *)src, (R *)dens);
                         if (k.mom == 2)
                             hipLaunchKernelGGL(
                                 (k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P, NODE, SR>), gc,
@@ -776,6 +799,9 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dn, NodeLaunch *sn,
                 auto set = [&](auto Nc, auto Sc) {
                     constexpr bool NODE = decltype(Nc)::value, SR = decltype(Sc)::value;
                     dn->func = (void *)&k_moments_buf<ST, LIN_BLOCK, NODE>;
+                    if constexpr (nt_all_form<ST, NODE>())
+                        if (pass1_nt_all(k, m.N))
+                            dn->func = (void *)&k_moments_buf<ST, LIN_BLOCK, false, PULL_NT_ALL>;
                     sn->func =
                         k.mom == 2
                             ? (void *)&k_collide_mom_lds<CL_TX, CL_TY, CL_ZC, O, ST, P, NODE, SR>
@@ -851,7 +877,7 @@ int resident_blocks(const void *f, int threads, unsigned shmem) {
 hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
                                  const Tile *d_tiles, int ntiles,
                                  const void *src, void *dst, void *dens,
-                                 int grid, hipStream_t st, int passes) {
+                                 int grid, hipStream_t st, int passes, bool nt_all) {
     const bool p1 = passes & 1, p2 = passes & 2;
     hipError_t err = hipErrorInvalidValue;
     dispatch_storage(k.storage, [&](auto stv) {
@@ -866,7 +892,13 @@ hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
             bool done = false;
             if constexpr (buf_form<D, ST>()) {
                 if (k.mom && !k.big) {
-                    if (p1)
+                    bool all = false;
+                    if constexpr (nt_all_form<ST, false>()) all = nt_all;
+                    if (p1 && all)
+                        hipLaunchKernelGGL((kb_moments_buf<ST, PULL_NT_ALL>), dim3(grid), b, 0, st,
+                                           d_members, d_tiles, ntiles, (const T *)src,
+                                           (R *)dens);
+                    else if (p1)
                         hipLaunchKernelGGL((kb_moments_buf<ST>), dim3(grid), b, 0, st,
                                            d_members, d_tiles, ntiles, (const T *)src,
                                            (R *)dens);
@@ -914,7 +946,7 @@ hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
 }
 
 bool node_batch_two_pass(const StepKey &k, int grid, NodeLaunch *dn,
-                         NodeLaunch *sn) {
+                         NodeLaunch *sn, NodeLaunch *dn_all) {
     bool ok = false;
     dispatch_storage(k.storage, [&](auto stv) {
         using ST = decltype(stv);
@@ -936,6 +968,11 @@ bool node_batch_two_pass(const StepKey &k, int grid, NodeLaunch *dn,
             dn->grid = sn->grid = dim3(grid);
             dn->block = sn->block = dim3(TP_BX, TP_BY, 1);
             dn->shmem = sn->shmem = 0;
+            if (dn_all) {
+                *dn_all = *dn;
+                if constexpr (buf_form<D, ST>() && nt_all_form<ST, false>())
+                    if (k.mom && !k.big) dn_all->func = (void *)&kb_moments_buf<ST, PULL_NT_ALL>;
+            }
             ok = true;
         });
     });

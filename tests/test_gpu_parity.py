@@ -451,6 +451,56 @@ def test_slab_pipelined_moment_pass_single_step(stencil, psi, g):
     assert worst < 1e-6, worst
 
 
+def test_nt_all_pass1_single_step_graph_and_batch():
+    """A lattice whose moment field (88 MB) is past the size from which pass 1
+    loads every population non-temporally, and below the slab threshold: one
+    step against the oracle site by site on every plane; 7 steps in graphs of
+    3 and in a batch (graphs of 3) beside a small member, whose chunk keeps the
+    default pass 1, give the bits of direct launches."""
+    nz, ny, nx, R0 = 144, 160, 160, 28.0
+    g = ((0.0, 1.8), (1.8, 0.0))
+    nA, nB = inputs.droplet(nx, ny, nz, R=R0)
+    p = scmc.problem(scmc.D3Q19, scmc.E6, (nz, ny, nx), g=g, storage=scmc.F32,
+                     kernel=scmc.KERNEL_TWO_PASS_MOM)
+    sim = scmc.Sim(p)
+    sim.scmc_set_density(nA, nB)
+    sim.scmc_step(1)
+    f1, _ = sim.scmc_get_populations()
+    sim.scmc_step(6)
+    direct = sim.scmc_get_fields()
+    sim.close()
+    o = O.Oracle(3, 6, (nz, ny, nx), g=g)
+    o.set_density(nA, nB)
+    xi, _ = scmc.velocities(scmc.D3Q19)
+    perm = _perm(scmc.D3Q19, 3)
+    worst = 0.0
+    for z in range(nz):
+        dz = abs(z - nz // 2)
+        rxy = np.sqrt(max(R0 * R0 - dz * dz, 0.0))
+        for (y, x) in ((ny // 2, int(nx // 2 + rxy)), (ny // 2 + int(rxy), nx // 2), (0, 0)):
+            want = o.collide_site((z * ny + y) * nx + x)[:, perm]
+            got = np.array([[f1[J, i, (z + xi[i, 2]) % nz, (y + xi[i, 1]) % ny,
+                                (x + xi[i, 0]) % nx] for i in range(19)] for J in range(2)])
+            worst = max(worst, np.abs(got - want).max())
+    assert worst < 1e-6, worst
+    del f1, o
+    gs = scmc.Sim(p)
+    gs.scmc_set_graph_steps(3)
+    gs.scmc_set_density(nA, nB)
+    gs.scmc_step(7)
+    assert np.array_equal(gs.scmc_get_fields(), direct)
+    gs.close()
+    q = scmc.problem(scmc.D3Q19, scmc.E6, (24, 28, 32), g=g, storage=scmc.F32,
+                     kernel=scmc.KERNEL_TWO_PASS_MOM)
+    bt = scmc.Batch([p, q])
+    bt.scmc_batch_set_graph_steps(3)
+    bt.scmc_batch_set_density(0, nA, nB)
+    bt.scmc_batch_set_density(1, *inputs.droplet(32, 28, 24, R=6.0))
+    bt.scmc_batch_step(7)
+    assert np.array_equal(bt.scmc_batch_get_fields(0), direct)
+    bt.close()
+
+
 def test_slab_pipelined_asymmetric_droplet_matches_oracle():
     """The 256^3 workload's arithmetic (D3Q19 / E6, psi = n, g_AA = -0.2,
     B-rich droplet, FP32) in its slab schedule on a 160 x 192 x 192 box, 200
