@@ -114,9 +114,10 @@ typedef enum {
                                      pulls and stores n_J and the momentum,
                                      the second collides from those moments
                                      without pulling again (every lattice,
-                                     stencil and storage; lattices with more
-                                     than 64 MB of moments run it in
-                                     z-slabs); with a nonzero
+                                     stencil and storage; lattices whose
+                                     moments (24 B per site) pass 264 MiB
+                                     in FP32, 128 MiB in FP16/BF16, run it
+                                     in z-slabs); with a nonzero
                                      tile (D3Q19, FP32/FP16/BF16) the second
                                      pass stages the stencil's concentrations
                                      in LDS (64 x 8 columns, z-chunks of 8) */

@@ -647,8 +647,13 @@ static void mom_blocks(const Member &m, bool lds, dim3 *gm, dim3 *bm, dim3 *gc,
 }
 
 // Slabs for lattices with more than kSlabMinMomentBytes of moments (24 B per
-// site); below that the whole moment field stays in the 256 MB Infinity Cache
-// between the passes.  A slab has at least the stencil's z-radius planes and
+// site; kSlabMinMomentBytesF32 for FP32 storage); below that enough of the
+// moment field stays in the 256 MiB Infinity Cache between the passes.  FP32
+// lattices get up to about that cache's size unslabbed, where their pass 1
+// loads every population non-temporally (pass1_nt_all): measured faster than
+// the slabs up to 224^3 (270 MB of moments) and slower from 228^3 (284 MB).
+// The 16-bit formats, whose pass 1 keeps the shifted populations cached,
+// measured faster in slabs from 208^3 on.  A slab has at least the stencil's z-radius planes and
 // about kSlabTouchBytes of traffic per pair of passes (moments written and
 // read, populations read and written: 352 B per site in FP32, 200 B in
 // FP16/BF16), so the slabs of the launches in flight stay cached.
@@ -662,12 +667,14 @@ static void mom_blocks(const Member &m, bool lds, dim3 *gm, dim3 *bm, dim3 *gc,
 // writes slab k+2, which it does not read.
 static constexpr size_t kSlabTouchBytes = (size_t)192 << 20;
 static constexpr size_t kSlabMinMomentBytes = (size_t)128 << 20;
+static constexpr size_t kSlabMinMomentBytesF32 = (size_t)264 << 20;
 
 std::vector<SlabOp> slab_schedule(const StepKey &k, const Member &m) {
     std::vector<SlabOp> ops;
     if (k.dim != 3 || k.storage == ST_F64 || k.mom != 1 || k.big || m.sr) return ops;
     const size_t sites = (size_t)m.nx * m.ny;
-    if (sites * 24 * m.nz <= kSlabMinMomentBytes) return ops;
+    const size_t min_bytes = k.storage == ST_F32 ? kSlabMinMomentBytesF32 : kSlabMinMomentBytes;
+    if (sites * 24 * m.nz <= min_bytes) return ops;
     const size_t pop = k.storage == ST_F32 ? 4 : 2;
     const size_t touch = 2 * 24 + 4 * 19 * pop + (k.node ? 24 : 0);
     const int rz = k.order == 4 ? 1 : 2;

@@ -414,14 +414,14 @@ _GC = -np.e ** 2 / 3.0
     (scmc.E6, scmc.PSI_N, ((-0.2, 1.8), (1.8, 0.0))),
     (scmc.E4, scmc.PSI_EXP_NEG_INV, ((_GC * 0.6, 0.5), (0.5, _GC * 0.6)))])
 def test_slab_pipelined_moment_pass_single_step(stencil, psi, g):
-    """A lattice whose moment field (142 MB) exceeds the slab threshold
-    (128 MB) runs the moment two-pass in z-slabs (eleven of 14-15 planes),
+    """An FP32 lattice whose moment field (288 MB) exceeds the slab threshold
+    (264 MiB in FP32) runs the moment two-pass in z-slabs (24 of 8-9 planes),
     pass 2 of each slab beside pass 1 of the slab after next in one launch.
     One step from a droplet against the oracle
     site by site, on every plane (so on both sides of every slab boundary),
     on the interface and in the bulk.  The asymmetric coupling g_AA = -0.2
     holds a B-rich droplet, as the 256^3 workload does."""
-    nz, ny, nx, R0 = 160, 192, 192, 30.0
+    nz, ny, nx, R0 = 208, 240, 240, 30.0
     if g[0][0] == -0.2:
         nA, nB = inputs.droplet(nx, ny, nz, R=R0, a_rich=False, bulk=inputs.FLAT_GUESS[-0.2])
     else:
@@ -503,11 +503,11 @@ def test_nt_all_pass1_single_step_graph_and_batch():
 
 def test_slab_pipelined_asymmetric_droplet_matches_oracle():
     """The 256^3 workload's arithmetic (D3Q19 / E6, psi = n, g_AA = -0.2,
-    B-rich droplet, FP32) in its slab schedule on a 160 x 192 x 192 box, 200
+    B-rich droplet, FP32) in its slab schedule on a 208 x 240 x 240 box, 200
     steps (in graphs of 8) against the oracle: every concentration, and
     Delta P, C_d and the pressure-tensor line.  FP32 rounding over 200
     steps of a relaxing droplet: 1e-5 in n, 1e-4 relative in the pressures."""
-    nz, ny, nx, R0, steps = 160, 192, 192, 30.0, 200
+    nz, ny, nx, R0, steps = 208, 240, 240, 30.0, 200
     g = ((-0.2, 1.8), (1.8, 0.0))
     nA, nB = inputs.droplet(nx, ny, nz, R=R0, a_rich=False, bulk=inputs.FLAT_GUESS[-0.2])
     sim = scmc.Sim(scmc.problem(scmc.D3Q19, scmc.E6, (nz, ny, nx), g=g, storage=scmc.F32))
@@ -536,7 +536,7 @@ def test_slab_pipelined_moment_pass_graph_and_fused():
     """The slab schedule in captured graphs equals direct launches bit for bit,
     and 20 steps agree with the fused moment-ring design (one launch per step,
     no slabs) to FP32 rounding."""
-    nz, ny, nx, R0 = 160, 192, 192, 30.0
+    nz, ny, nx, R0 = 208, 240, 240, 30.0
     nA, nB = inputs.droplet(nx, ny, nz, R=R0)
     runs = {}
     for name, kernel, tile, graph in (("direct", scmc.KERNEL_AUTO, (0, 0, 0), 0),
