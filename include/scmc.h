@@ -331,9 +331,11 @@ int scmc_flat_equilibrium(const scmc_problem *p, int lx, const double *guess,
 
 /* Many independent lattices advanced together over one tile list (the
  * paper's sweep over droplet sizes and couplings, Sec. 4).  The moment
- * two-pass runs the members in chunks, one workgroup per 256-site tile, pass
- * 2 of a chunk in the same launch as pass 1 of the next; the fused designs
- * run one persistent launch per step.  Members may differ in size and
+ * two-pass runs the members in chunks of whole members (a member with 48 MB
+ * or more of moments alone, the others packed up to 48 MB), pass 1 and then
+ * pass 2 of each chunk: a chunk of one member launches as a single lattice
+ * does, the others one workgroup per 256-site tile.  The fused designs run
+ * one persistent launch per step.  Members may differ in size and
  * couplings; they must share lattice, stencil, tau and storage.  Member calls
  * take the member index i. */
 typedef struct scmc_batch scmc_batch;

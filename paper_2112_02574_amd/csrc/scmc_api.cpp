@@ -212,9 +212,13 @@ struct scmc_sim {
 
 // One launch of the batched two-pass: pass 1 or 2 over tiles [t0, t0 + n),
 // one workgroup per tile; nt_all: pass 1 with every load non-temporal.
+// member >= 0: the chunk is that member alone, launched like a single
+// lattice (launch_member_pass, with m its description) instead.
 struct BatchOp {
     int pass, t0, n;
     bool nt_all = false;
+    int member = -1;
+    Member m{};
 };
 
 struct scmc_batch {
@@ -865,8 +869,11 @@ int direct_step_batch(scmc_batch *b) {
     }
     for (size_t k = 0; e == hipSuccess && k < b->ops.size(); ++k) {
         const BatchOp &o = b->ops[k];
-        e = launch_batch_two_pass(c.key, b->d_members, b->d_tiles + o.t0, o.n, src, dst, c.dens,
-                                  o.n, c.stream, o.pass, o.nt_all);
+        e = o.member >= 0 ? launch_member_pass(c.key, o.m, src, dst, c.dens, o.pass, o.nt_all,
+                                               c.stream)
+                          : launch_batch_two_pass(c.key, b->d_members, b->d_tiles + o.t0, o.n,
+                                                  src, dst, c.dens, o.n, c.stream, o.pass,
+                                                  o.nt_all);
     }
     if (e != hipSuccess)
         return fail(c, SCMC_EDEVICE, "batch step launch: %s",
@@ -931,6 +938,19 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
                                          (void *)&dstv, (void *)&densv};
             for (const BatchOp &o : *ops) {
                 if (rc) break;
+                if (o.member >= 0) {  // a chunk of one member, as a single lattice
+                    NodeLaunch ml{};
+                    if (!node_member_pass(c.key, o.m, o.pass, o.nt_all, &ml)) {
+                        rc = fail(c, SCMC_EUNSUPPORTED, "no graph node for a member pass");
+                        break;
+                    }
+                    Member mv = o.m;
+                    std::vector<void *> margs = {(void *)&mv, (void *)&srcv};
+                    if (o.pass == 2) margs.push_back((void *)&dstv);
+                    margs.push_back((void *)&densv);
+                    rc = add(ml, margs);
+                    continue;
+                }
                 dt = d_tiles + o.t0;
                 nt = o.n;
                 NodeLaunch nl = o.pass == 1 ? (o.nt_all ? dna : dn) : sn;
@@ -1591,8 +1611,10 @@ static int batch_tiles(const std::vector<scmc_problem> &ps, int kernel,
 // The launches of a two-pass step: pass 1 and then pass 2 of each chunk in
 // turn, so that pass 2 finds the chunk's moments still cached.  (Sharing a
 // launch between pass 2 of one chunk and pass 1 of the next measured no
-// faster.)  The fused designs (one persistent launch), the density two-pass
-// and stochastic rounding (whose step counter advances at the first tile of
+// faster.)  A chunk of one member runs the single-lattice kernels with that
+// member's description as an argument (no per-block tile and member loads).
+// The fused designs (one persistent launch), the density two-pass and
+// stochastic rounding (whose step counter advances at the first tile of
 // pass 1) run pass 1 and then pass 2 over the whole list.
 static void batch_set_ops(scmc_batch *b) {
     const Common &c = b->c;
@@ -1612,8 +1634,14 @@ static void batch_set_ops(scmc_batch *b) {
                 n += (b->lats[i].m.N + 255) / 256;  // tiles of batch_tiles
                 sites += b->lats[i].m.N;
             }
-            ops.push_back({1, t, n, pass1_nt_all(c.key, sites)});
-            ops.push_back({2, t, n});
+            BatchOp p1{1, t, n, pass1_nt_all(c.key, sites)}, p2{2, t, n};
+            NodeLaunch probe{};
+            if (chunk.size() == 1 && node_member_pass(c.key, b->lats[chunk[0]].m, 1, false, &probe)) {
+                p1.member = p2.member = chunk[0];
+                p1.m = p2.m = b->lats[chunk[0]].m;
+            }
+            ops.push_back(p1);
+            ops.push_back(p2);
             t += n;
         }
         if (t != b->ntiles) ops.clear();

@@ -123,6 +123,16 @@ bool node_two_pass(const StepKey &k, NodeLaunch *dens_node,
                    NodeLaunch *step_node, const Member &m);
 bool node_fused(const StepKey &k, const int *tile, NodeLaunch *node,
                 const Member &m);
+// One pass (1 or 2) of the moment two-pass over the whole of one batch member,
+// launched like a single lattice (linear 256-site blocks, the member's
+// description a kernel argument instead of a per-block load from the tile
+// list).  D3Q19 buffer forms without node storage or stochastic rounding;
+// node_member_pass returns false (launch_member_pass hipErrorNotSupported)
+// for every other key.  nt_all as in launch_batch_two_pass.
+bool node_member_pass(const StepKey &k, const Member &m, int pass, bool nt_all,
+                      NodeLaunch *node);
+hipError_t launch_member_pass(const StepKey &k, const Member &m, const void *src, void *dst,
+                              void *dens, int pass, bool nt_all, hipStream_t st);
 // dens_node_nt_all (optional): the pass-1 node of launch_batch_two_pass's
 // nt_all form (the same as dens_node where there is none)
 bool node_batch_two_pass(const StepKey &k, int grid, NodeLaunch *dens_node,

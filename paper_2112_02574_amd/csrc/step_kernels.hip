@@ -952,6 +952,46 @@ hipError_t launch_batch_two_pass(const StepKey &k, const Member *d_members,
     return err;
 }
 
+bool node_member_pass(const StepKey &k, const Member &m, int pass, bool nt_all,
+                      NodeLaunch *nl) {
+    bool ok = false;
+    if (k.node || k.sr || !k.mom || k.big) return false;
+    dispatch_storage(k.storage, [&](auto stv) {
+        using ST = decltype(stv);
+        dispatch_shape<ST>(k, [&](auto Dc, auto Oc, auto Pc) {
+            constexpr int D = decltype(Dc)::value;
+            constexpr int O = decltype(Oc)::value;
+            constexpr int P = decltype(Pc)::value;
+            if constexpr (buf_form<D, ST>()) {
+                nl->grid = dim3(linear_blocks(m, m.znum, LIN_BLOCK));
+                nl->block = dim3(LIN_BLOCK, 1, 1);
+                nl->shmem = 0;
+                if (pass == 1) {
+                    nl->func = (void *)&k_moments_buf<ST, LIN_BLOCK>;
+                    if constexpr (nt_all_form<ST, false>())
+                        if (nt_all) nl->func = (void *)&k_moments_buf<ST, LIN_BLOCK, false, PULL_NT_ALL>;
+                } else {
+                    nl->func = (void *)&k_collide_mom_buf<O, ST, P, LIN_BLOCK>;
+                }
+                ok = true;
+            }
+        });
+    });
+    return ok;
+}
+
+hipError_t launch_member_pass(const StepKey &k, const Member &m, const void *src, void *dst,
+                              void *dens, int pass, bool nt_all, hipStream_t st) {
+    NodeLaunch nl{};
+    if (!node_member_pass(k, m, pass, nt_all, &nl)) return hipErrorNotSupported;
+    Member mv = m;
+    const void *srcv = src;
+    void *dstv = dst, *densv = dens;
+    void *a1[] = {(void *)&mv, (void *)&srcv, (void *)&densv};
+    void *a2[] = {(void *)&mv, (void *)&srcv, (void *)&dstv, (void *)&densv};
+    return hipLaunchKernel(nl.func, nl.grid, nl.block, pass == 1 ? a1 : a2, 0, st);
+}
+
 bool node_batch_two_pass(const StepKey &k, int grid, NodeLaunch *dn,
                          NodeLaunch *sn, NodeLaunch *dn_all) {
     bool ok = false;
