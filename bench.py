@@ -158,10 +158,12 @@ def summarize_profiles(outdir, tag="f32", L=128):
     if tag == "batch48":
         # the batch's two-pass launches (its process also runs the FP64 flat
         # stages and the autotuner's candidates): one pass 1 and one pass 2
-        # per member chunk, so a step is the period of the launch sequence;
-        # the step time is the mean over the trace run's last 300 steps
+        # per member chunk (tile-list kernels kb_*, or for a chunk of one
+        # member the single-lattice ones), so a step is the period of the
+        # launch sequence; the step time is the mean over the trace run's
+        # last 300 steps
         seq = [r for r in rows(f"prof{sub}_trace", "_kernel_trace.csv")
-               if re.search(r"scmc::kb_(moments|collide_mom)(_buf)?<", r["Kernel_Name"])]
+               if re.search(r"scmc::kb?_(moments|collide_mom)_buf<", r["Kernel_Name"])]
         seq.sort(key=lambda r: int(r["Start_Timestamp"]))
         key = [(r["Kernel_Name"], r["Grid_Size_X"]) for r in seq]
         per_step = next(p for p in range(1, len(key) // 300 + 1)
@@ -234,8 +236,9 @@ def summarize_profiles(outdir, tag="f32", L=128):
               "%.3f x the algorithmic %.1f MB." % (
                   fetch, sf, write, sw, hbm / 1e6, hbm / (bps * N), bps * N / 1e6), ""]
     if tag == "batch48":
-        lines[-1:-1] = ["A batch step launches pass 1 and pass 2 once per member chunk (%d launches, one "
-                        "workgroup per 256-site tile); the step time is the launches' summed duration "
+        lines[-1:-1] = ["A batch step launches pass 1 and pass 2 once per member chunk (%d launches: a "
+                        "chunk of one member as a single lattice, the others one workgroup per 256-site "
+                        "tile); the step time is the launches' summed duration "
                         "over the trace run's last 300 steps, divided by 300, and the trace's averages "
                         "above are per chunk." % per_step, ""]
     with open(trace_md, "w") as fh:
