@@ -158,19 +158,29 @@ def summarize_profiles(outdir, tag="f32", L=128):
     if tag == "batch48":
         # the batch's two-pass launches (its process also runs the FP64 flat
         # stages and the autotuner's candidates): one pass 1 and one pass 2
-        # per member chunk (tile-list kernels kb_*, or for a chunk of one
-        # member the single-lattice ones), so a step is the period of the
-        # launch sequence; the step time is the mean over the trace run's
-        # last 300 steps
+        # per member chunk and step (tile-list kernels kb_*, or for a chunk
+        # of one member the single-lattice ones), several steps chunk by
+        # chunk.  The trace run's last 300 steps are the launches from the
+        # end back to where the pass-1 launches have covered every member's
+        # sites (in 256-site blocks) 300 times; the step time is their
+        # summed duration over 300
         seq = [r for r in rows(f"prof{sub}_trace", "_kernel_trace.csv")
                if re.search(r"scmc::kb?_(moments|collide_mom)_buf<", r["Kernel_Name"])]
         seq.sort(key=lambda r: int(r["Start_Timestamp"]))
-        key = [(r["Kernel_Name"], r["Grid_Size_X"]) for r in seq]
-        per_step = next(p for p in range(1, len(key) // 300 + 1)
-                        if key[-300 * p:] == key[-p:] * 300)
-        names = sorted({r["Kernel_Name"].split("(")[0] for r in seq[-per_step:]})
+        need = 300 * sum(-(-m["L"] ** 3 // 256) * 256 for m in inputs.batch_members())
+        got, i = 0, len(seq)
+        while got < need and i > 0:
+            i -= 1
+            if "moments" in seq[i]["Kernel_Name"]:
+                got += (int(seq[i]["Grid_Size_X"]) * int(seq[i]["Grid_Size_Y"])
+                        * int(seq[i]["Grid_Size_Z"]))
+        if got != need:
+            raise SystemExit(f"batch trace: pass-1 launches cover {got} sites, not {need}")
+        window = seq[i:]
+        per_step = round(len(window) / 300)
+        names = sorted({r["Kernel_Name"].split("(")[0] for r in window})
         step_us = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-                      for r in seq[-300 * per_step:]) / 300 / 1e3
+                      for r in window) / 300 / 1e3
     fetch = write = 0.0
     nf = nw = 0
     have_counters = os.path.isdir(os.path.join(outdir, f"prof{sub}_fetch")) and any(

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
+#include <type_traits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -858,6 +860,15 @@ int direct_step_sim(scmc_sim *s) {
     return SCMC_OK;
 }
 
+hipError_t launch_op(scmc_batch *b, const BatchOp &o, const void *src, void *dst) {
+    const Common &c = b->c;
+    return o.member >= 0 ? launch_member_pass(c.key, o.m, src, dst, c.dens, o.pass, o.nt_all,
+                                              c.stream)
+                         : launch_batch_two_pass(c.key, b->d_members, b->d_tiles + o.t0, o.n,
+                                                 src, dst, c.dens, o.n, c.stream, o.pass,
+                                                 o.nt_all);
+}
+
 int direct_step_batch(scmc_batch *b) {
     Common &c = b->c;
     const void *src = c.pop[c.cur];
@@ -867,18 +878,41 @@ int direct_step_batch(scmc_batch *b) {
         e = launch_batch_fused(c.key, b->d_members, b->d_tiles, b->ntiles, src, dst, c.tile,
                                b->grid, c.stream);
     }
-    for (size_t k = 0; e == hipSuccess && k < b->ops.size(); ++k) {
-        const BatchOp &o = b->ops[k];
-        e = o.member >= 0 ? launch_member_pass(c.key, o.m, src, dst, c.dens, o.pass, o.nt_all,
-                                               c.stream)
-                          : launch_batch_two_pass(c.key, b->d_members, b->d_tiles + o.t0, o.n,
-                                                  src, dst, c.dens, o.n, c.stream, o.pass,
-                                                  o.nt_all);
-    }
+    for (size_t k = 0; e == hipSuccess && k < b->ops.size(); ++k)
+        e = launch_op(b, b->ops[k], src, dst);
     if (e != hipSuccess)
         return fail(c, SCMC_EDEVICE, "batch step launch: %s",
                     hipGetErrorString(e));
     c.cur ^= 1;
+    return SCMC_OK;
+}
+
+// k steps of the batched two-pass, chunk by chunk: each chunk (the pass 1 and
+// pass 2 ops that batch_set_ops pairs) advances k steps before the next one
+// starts.  Members are independent lattices, so the order changes no bit of
+// any member's result, and every member is k steps further on return; a
+// chunk's next pass 1 then reads the populations its pass 2 has just
+// written, part of them still in the Infinity Cache, as a lattice stepped on
+// its own does.  The fused design (no ops) runs step by step.
+int direct_steps_batch(scmc_batch *b, int64_t k) {
+    Common &c = b->c;
+    if (b->ops.empty()) {
+        for (int64_t t = 0; t < k; ++t) {
+            const int rc = direct_step_batch(b);
+            if (rc) return rc;
+        }
+        return SCMC_OK;
+    }
+    hipError_t e = hipSuccess;
+    for (size_t j = 0; e == hipSuccess && j + 1 < b->ops.size(); j += 2)
+        for (int64_t t = 0; e == hipSuccess && t < k; ++t) {
+            const int cu = c.cur ^ (int)(t & 1);
+            e = launch_op(b, b->ops[j], c.pop[cu], c.pop[1 - cu]);
+            if (e == hipSuccess) e = launch_op(b, b->ops[j + 1], c.pop[cu], c.pop[1 - cu]);
+        }
+    if (e != hipSuccess)
+        return fail(c, SCMC_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
+    if (k & 1) c.cur ^= 1;
     return SCMC_OK;
 }
 
@@ -919,47 +953,49 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
         return SCMC_OK;
     };
     int cur = par, rc = SCMC_OK;
-    for (int t = 0; t < k && !rc; ++t) {
-        if (ops) {  // the two-pass launches of direct_step_batch
-            NodeLaunch dn{}, sn{}, dna{};
-            if (!node_batch_two_pass(c.key, 1, &dn, &sn, &dna)) {
-                rc = fail(c, SCMC_EUNSUPPORTED, "no graph node for this kernel");
-                break;
-            }
-            const Member *dm = d_members;
-            const Tile *dt = d_tiles;
-            int nt = 0;
-            const void *srcv = c.pop[cur];
-            void *dstv = c.pop[1 - cur];
-            void *densv = c.dens;
-            std::vector<void *> dargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
-                                         (void *)&densv};
-            std::vector<void *> sargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
-                                         (void *)&dstv, (void *)&densv};
-            for (const BatchOp &o : *ops) {
-                if (rc) break;
-                if (o.member >= 0) {  // a chunk of one member, as a single lattice
-                    NodeLaunch ml{};
-                    if (!node_member_pass(c.key, o.m, o.pass, o.nt_all, &ml)) {
-                        rc = fail(c, SCMC_EUNSUPPORTED, "no graph node for a member pass");
-                        break;
+    if (ops) {  // the two-pass launches of direct_steps_batch: chunk by chunk, k steps each
+        NodeLaunch dn{}, sn{}, dna{};
+        if (!node_batch_two_pass(c.key, 1, &dn, &sn, &dna))
+            rc = fail(c, SCMC_EUNSUPPORTED, "no graph node for this kernel");
+        const Member *dm = d_members;
+        const Tile *dt = d_tiles;
+        int nt = 0;
+        const void *srcv = nullptr;
+        void *dstv = nullptr;
+        void *densv = c.dens;
+        std::vector<void *> dargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
+                                     (void *)&densv};
+        std::vector<void *> sargs = {(void *)&dm, (void *)&dt, (void *)&nt, (void *)&srcv,
+                                     (void *)&dstv, (void *)&densv};
+        for (size_t j = 0; !rc && j + 1 < ops->size(); j += 2)
+            for (int t = 0; !rc && t < k; ++t) {
+                const int cu = par ^ (t & 1);
+                srcv = c.pop[cu];
+                dstv = c.pop[1 - cu];
+                for (size_t q = j; !rc && q < j + 2; ++q) {
+                    const BatchOp &o = (*ops)[q];
+                    if (o.member >= 0) {  // a chunk of one member, as a single lattice
+                        NodeLaunch ml{};
+                        if (!node_member_pass(c.key, o.m, o.pass, o.nt_all, &ml)) {
+                            rc = fail(c, SCMC_EUNSUPPORTED, "no graph node for a member pass");
+                            break;
+                        }
+                        Member mv = o.m;
+                        std::vector<void *> margs = {(void *)&mv, (void *)&srcv};
+                        if (o.pass == 2) margs.push_back((void *)&dstv);
+                        margs.push_back((void *)&densv);
+                        rc = add(ml, margs);
+                        continue;
                     }
-                    Member mv = o.m;
-                    std::vector<void *> margs = {(void *)&mv, (void *)&srcv};
-                    if (o.pass == 2) margs.push_back((void *)&dstv);
-                    margs.push_back((void *)&densv);
-                    rc = add(ml, margs);
-                    continue;
+                    dt = d_tiles + o.t0;
+                    nt = o.n;
+                    NodeLaunch nl = o.pass == 1 ? (o.nt_all ? dna : dn) : sn;
+                    nl.grid = dim3(nt);  // one workgroup per tile
+                    rc = add(nl, o.pass == 1 ? dargs : sargs);
                 }
-                dt = d_tiles + o.t0;
-                nt = o.n;
-                NodeLaunch nl = o.pass == 1 ? (o.nt_all ? dna : dn) : sn;
-                nl.grid = dim3(nt);  // one workgroup per tile
-                rc = add(nl, o.pass == 1 ? dargs : sargs);
             }
-            cur ^= 1;
-            continue;
-        }
+    }
+    for (int t = 0; !ops && t < k && !rc; ++t) {
         for (size_t ch = 0; ch + 1 < chunks.size() && !rc; ++ch) {
             const int ntiles = chunks[ch + 1] - chunks[ch];
             // persistent fused launches: at most `grid` workgroups (clamped to
@@ -1049,8 +1085,12 @@ int build_graph(Common &c, int k, int par, bool batch, const Member &m,
     return SCMC_OK;
 }
 
-template <class StepFn, class BuildFn>
-int run_steps(Common &c, int64_t nsteps, StepFn direct, BuildFn build) {
+// Steps outside graphs go one at a time through direct(), or, where many is
+// given, in blocks of up to kStepBlock steps through many(k).
+constexpr int64_t kStepBlock = 64;
+
+template <class StepFn, class BuildFn, class ManyFn = std::nullptr_t>
+int run_steps(Common &c, int64_t nsteps, StepFn direct, BuildFn build, ManyFn many = nullptr) {
     if (nsteps < 0) return fail(c, SCMC_EINVAL, "nsteps < 0");
     if (!c.initialized)
         return fail(c, SCMC_ESTATE, "state not set (call set_density first)");
@@ -1065,6 +1105,12 @@ int run_steps(Common &c, int64_t nsteps, StepFn direct, BuildFn build) {
             if (c.graph_k % 2) c.cur ^= 1;
             left -= c.graph_k;
             c.step += c.graph_k;
+        } else if constexpr (!std::is_same<ManyFn, std::nullptr_t>::value) {
+            const int64_t k = std::min(left, kStepBlock);
+            int rc = many(k);
+            if (rc) return rc;
+            left -= k;
+            c.step += k;
         } else {
             int rc = direct();
             if (rc) return rc;
@@ -1609,7 +1655,8 @@ static int batch_tiles(const std::vector<scmc_problem> &ps, int kernel,
 }
 
 // The launches of a two-pass step: pass 1 and then pass 2 of each chunk in
-// turn, so that pass 2 finds the chunk's moments still cached.  (Sharing a
+// turn (ops[2i] and ops[2i + 1]; several steps run chunk by chunk, see
+// direct_steps_batch), so that pass 2 finds the chunk's moments still cached.  (Sharing a
 // launch between pass 2 of one chunk and pass 1 of the next measured no
 // faster.)  A chunk of one member runs the single-lattice kernels with that
 // member's description as an argument (no per-block tile and member loads).
@@ -1829,7 +1876,8 @@ int scmc_batch_step(scmc_batch *b, int64_t nsteps) {
             return build_graph(c, c.graph_k, par, true, Member{}, b->d_members, b->d_tiles,
                                whole, b->grid,
                                c.kernel == SCMC_KERNEL_FUSED ? nullptr : &b->ops);
-        });
+        },
+        [&](int64_t k) { return direct_steps_batch(b, k); });
 }
 
 int scmc_batch_get_fields(scmc_batch *b, int i, double *nA, double *nB,
