@@ -345,6 +345,11 @@ int scmc_batch_create(const scmc_problem *ps, int count, void *d_ws,
 int scmc_batch_destroy(scmc_batch *b);  /* waits for the stream, as scmc_destroy */
 int scmc_batch_set_density(scmc_batch *b, int i, const double *nA,
                            const double *nB);
+/* Advances every member nsteps steps.  Members are independent lattices:
+ * with the moment two-pass a call runs chunk by chunk, each chunk a block of
+ * steps (a graph's length, else up to 64) before the next, so members pass
+ * through different steps while the call's work runs on the stream; all
+ * are at the batch's step count once it has completed. */
 int scmc_batch_step(scmc_batch *b, int64_t nsteps);
 int scmc_batch_set_graph_steps(scmc_batch *b, int k);
 int scmc_batch_get_fields(scmc_batch *b, int i, double *nA, double *nB,
