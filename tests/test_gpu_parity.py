@@ -304,14 +304,16 @@ def test_batch_matches_single_runs():
         s.close()
 
 
+@pytest.mark.parametrize("storage", [scmc.F32, scmc.F16_OFF])
 @pytest.mark.parametrize("graph_steps", [0, 4])
-def test_batch_in_member_chunks_matches_single_runs(graph_steps):
+def test_batch_in_member_chunks_matches_single_runs(graph_steps, storage):
     """Members whose moment fields exceed the chunk budget (48 MB: here
-    128^3 | 128^3 | 112^3 + 48^3) run the moment two-pass chunk by chunk;
-    direct launches and graphs must still equal single-lattice runs bit for
-    bit."""
+    128^3 | 128^3 | 112^3 + 48^3) run the moment two-pass chunk by chunk, the
+    128^3 ones each alone with the single-lattice kernels, several steps per
+    chunk; direct launches and graphs must still equal single-lattice runs
+    bit for bit, in FP32 and with FP16 offsets."""
     members = [(128, 24.0, True), (128, 20.0, False), (112, 18.0, True), (48, 8.0, False)]
-    ps = [scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), storage=scmc.F32) for L, _, _ in members]
+    ps = [scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), storage=storage) for L, _, _ in members]
     inits = [inputs.droplet(L, L, L, R=R0, a_rich=a) for L, R0, a in members]
     b = scmc.Batch(ps)
     for i, (nA, nB) in enumerate(inits):
@@ -319,7 +321,7 @@ def test_batch_in_member_chunks_matches_single_runs(graph_steps):
     b.scmc_batch_set_graph_steps(graph_steps)
     b.scmc_batch_step(10)
     for i, (nA, nB) in enumerate(inits):
-        print(f"member {i} graph_steps {graph_steps}", flush=True)
+        print(f"member {i} graph_steps {graph_steps} storage {storage}", flush=True)
         s = scmc.Sim(ps[i])
         s.scmc_set_density(nA, nB)
         s.scmc_step(10)
