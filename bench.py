@@ -629,7 +629,10 @@ def run(args):
                    "storage": args.storage,
                    "sites": N, "kernel": KERNEL_NAMES[kernel],
                    "tile": list(tile), "graph_steps": args.graph,
-                   "reductions_every": OBS_EVERY, "parallelism": "single GPU"},
+                   "reductions_every": OBS_EVERY, "parallelism": "single GPU",
+                   # the per-site sums (n_J, momentum, force, the mass closure)
+                   # accumulate FP32 values in FP64, order-free
+                   "site_sums": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel_ms": round(kernel_ms, 5),
