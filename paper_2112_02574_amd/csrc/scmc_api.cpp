@@ -1683,7 +1683,8 @@ static void batch_set_ops(scmc_batch *b) {
             }
             BatchOp p1{1, t, n, pass1_nt_all(c.key, sites)}, p2{2, t, n};
             NodeLaunch probe{};
-            if (chunk.size() == 1 && node_member_pass(c.key, b->lats[chunk[0]].m, 1, false, &probe)) {
+            if (chunk.size() == 1 &&
+                node_member_pass(c.key, b->lats[chunk[0]].m, 1, false, &probe)) {
                 p1.member = p2.member = chunk[0];
                 p1.m = p2.m = b->lats[chunk[0]].m;
             }

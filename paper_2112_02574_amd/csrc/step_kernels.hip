@@ -653,14 +653,14 @@ static void mom_blocks(const Member &m, bool lds, dim3 *gm, dim3 *bm, dim3 *gc,
 // loads every population non-temporally (pass1_nt_all): measured faster than
 // the slabs up to 224^3 (270 MB of moments) and slower from 228^3 (284 MB).
 // The 16-bit formats, whose pass 1 keeps the shifted populations cached,
-// measured faster in slabs from 208^3 on.  A slab has at least the stencil's z-radius planes and
-// about kSlabTouchBytes of traffic per pair of passes (moments written and
-// read, populations read and written: 352 B per site in FP32, 200 B in
-// FP16/BF16), so the slabs of the launches in flight stay cached.
-// Stochastic rounding keeps whole launches (its step counter advances at the
-// first block of pass 1).  Pass 2 of slab k needs the
-// moments of slabs k-1..k+1, and pass 1 only reads the source buffer, which no
-// pass 2 writes.  n slabs run in n + 2 launches:
+// measured faster in slabs from 208^3 on.  A slab has at least the stencil's
+// z-radius planes and about kSlabTouchBytes of traffic per pair of passes
+// (moments written and read, populations read and written: 352 B per site in
+// FP32, 200 B in FP16/BF16), so the slabs of the launches in flight stay
+// cached.  Stochastic rounding keeps whole launches (its step counter
+// advances at the first block of pass 1).  Pass 2 of slab k needs the
+// moments of slabs k-1..k+1, and pass 1 only reads the source buffer, which
+// no pass 2 writes.  n slabs run in n + 2 launches:
 //   P1(n-1);  P1(0..1);  then for k = 0..n-1 one launch of P2(k) together
 //   with P1(k+2) while k+2 <= n-2 (k_slab_pair), P2(k) alone after that.
 // Pass 2 of slab k then finds slabs k-1..k+1 done, and the pass 1 beside it
@@ -969,7 +969,8 @@ bool node_member_pass(const StepKey &k, const Member &m, int pass, bool nt_all,
                 if (pass == 1) {
                     nl->func = (void *)&k_moments_buf<ST, LIN_BLOCK>;
                     if constexpr (nt_all_form<ST, false>())
-                        if (nt_all) nl->func = (void *)&k_moments_buf<ST, LIN_BLOCK, false, PULL_NT_ALL>;
+                        if (nt_all)
+                            nl->func = (void *)&k_moments_buf<ST, LIN_BLOCK, false, PULL_NT_ALL>;
                 } else {
                     nl->func = (void *)&k_collide_mom_buf<O, ST, P, LIN_BLOCK>;
                 }
