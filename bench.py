@@ -20,8 +20,8 @@ HBM peak), the HBM traffic measured by rocprofv3 counters for the same
 kernel source when available, and the FP64 CPU oracle timed on a bounded
 sample of the same workload.  Beside it go the step rates of the other
 storage formats (FP64, FP16 and BF16 offsets) on the same droplet and of the
-48-member batched sweep (one persistent launch per step), each over a short
-timed run.
+48-member batched sweep (the moment two-pass over member chunks, in 64-step
+graphs), each over a short timed run.
 """
 import argparse
 import csv
@@ -485,7 +485,7 @@ def variants(args, L, R0, bulk, init, dev, stream):
 
 def _batch_rate(args, bulk, bulk_asym, dev, stream, steps, graph=64):
     """The batched sweep: 48 droplets on 48^3..160^3 boxes, symmetric and
-    asymmetric couplings, FP32, one persistent launch per step, graphs of
+    asymmetric couplings, FP32, the design the batch autotuner picks, graphs of
     ``graph`` steps (0: direct launches); step rate over ``steps`` timed
     steps."""
     from paper_2112_02574_amd import inputs
