@@ -330,6 +330,30 @@ def test_batch_in_member_chunks_matches_single_runs(graph_steps, storage):
     b.close()
 
 
+@pytest.mark.parametrize("graph_steps", [0, 5])
+def test_batch_long_call_matches_single_runs(graph_steps):
+    """One call of 70 steps runs chunk by chunk in blocks (direct launches: 64
+    steps and then 6; graphs of 5: fourteen replays), the 128^3 member alone
+    in its chunk, the others together; every member equals its single run
+    bit for bit."""
+    members = [(128, 24.0, True), (40, 8.0, False), (24, 6.0, True)]
+    ps = [scmc.problem(scmc.D3Q19, scmc.E6, (L, L, L), storage=scmc.F32) for L, _, _ in members]
+    inits = [inputs.droplet(L, L, L, R=R0, a_rich=a) for L, R0, a in members]
+    b = scmc.Batch(ps)
+    for i, (nA, nB) in enumerate(inits):
+        b.scmc_batch_set_density(i, nA, nB)
+    b.scmc_batch_set_graph_steps(graph_steps)
+    b.scmc_batch_step(70)
+    for i, (nA, nB) in enumerate(inits):
+        s = scmc.Sim(ps[i])
+        s.scmc_set_density(nA, nB)
+        s.scmc_step(70)
+        assert np.array_equal(b.scmc_batch_get_fields(i), s.scmc_get_fields()), i
+        s.close()
+    assert b.scmc_batch_get_populations(2)[1] == 70
+    b.close()
+
+
 G_SYM = ((0.0, 1.8), (1.8, 0.0))
 G_ASYM = ((-0.2, 1.8), (1.8, 0.0))
 
